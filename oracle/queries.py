@@ -1,0 +1,307 @@
+"""Geometric queries built on RangeBound (oracle; test infrastructure only).
+
+* :func:`classify`      -- Procedure 1 steps 4-6.
+* :func:`octree_build`  -- Procedure 3 run as breadth-first parallel rounds to
+  a fixed depth (Section 4.5 and the fixed-depth option used for mesh
+  extraction, Section 4.7), octree (arity 8) or k-d (arity 2) splits.
+* :func:`cast_rays`     -- Procedure 2 with the Appendix B step safety factor.
+* :func:`closest_point` -- Section 4.10 lazy best-first descent.
+"""
+from __future__ import annotations
+
+import heapq
+import math
+
+import numpy as np
+
+from . import mlp
+
+UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
+
+
+def classify(lo, hi):
+    """POSITIVE if lo > 0, NEGATIVE if hi < 0, else UNKNOWN (strict)."""
+    lab = np.full(np.shape(lo), UNKNOWN, dtype=np.uint8)
+    lab[np.asarray(lo) > 0.0] = POSITIVE
+    lab[np.asarray(hi) < 0.0] = NEGATIVE
+    return lab
+
+
+def range_bound(net, lo, hi, policy="truncate", k=31):
+    """(lo_y, hi_y, label) for each axis-aligned box."""
+    _, _, ly, hy = mlp.bound_boxes(net, lo, hi, policy, k)
+    return ly, hy, classify(ly, hy)
+
+
+# ---------------------------------------------------------------------------
+# Cells: Morton codes (bit b of the x index at position 3b, y at 3b+1, z at
+# 3b+2).  The 8 children of code c are (c << 3) | octant with octant =
+# dx | dy << 1 | dz << 2.
+# ---------------------------------------------------------------------------
+
+def morton_encode(ix, iy, iz, level):
+    ix = np.asarray(ix, dtype=np.uint64)
+    iy = np.asarray(iy, dtype=np.uint64)
+    iz = np.asarray(iz, dtype=np.uint64)
+    code = np.zeros(ix.shape, dtype=np.uint64)
+    for b in range(level):
+        bb = np.uint64(b)
+        one = np.uint64(1)
+        code |= ((ix >> bb) & one) << np.uint64(3 * b)
+        code |= ((iy >> bb) & one) << np.uint64(3 * b + 1)
+        code |= ((iz >> bb) & one) << np.uint64(3 * b + 2)
+    return code
+
+
+def morton_decode(code, level):
+    code = np.asarray(code, dtype=np.uint64)
+    ix = np.zeros(code.shape, dtype=np.int64)
+    iy = np.zeros(code.shape, dtype=np.int64)
+    iz = np.zeros(code.shape, dtype=np.int64)
+    one = np.uint64(1)
+    for b in range(level):
+        ix |= (((code >> np.uint64(3 * b)) & one).astype(np.int64)) << b
+        iy |= (((code >> np.uint64(3 * b + 1)) & one).astype(np.int64)) << b
+        iz |= (((code >> np.uint64(3 * b + 2)) & one).astype(np.int64)) << b
+    return ix, iy, iz
+
+
+def cell_bounds(code, level, dom_lo, dom_hi):
+    """float64 bounds of octree cells at ``level`` over the domain box."""
+    ix, iy, iz = morton_decode(code, level)
+    dom_lo = np.asarray(dom_lo, dtype=np.float64)
+    dom_hi = np.asarray(dom_hi, dtype=np.float64)
+    size = (dom_hi - dom_lo) / float(1 << level)
+    idx = np.stack([ix, iy, iz], axis=1).astype(np.float64)
+    lo = dom_lo + idx * size
+    hi = dom_lo + (idx + 1.0) * size
+    return lo, hi
+
+
+def kd_axes(depth, dom_lo, dom_hi):
+    """Split axis at every k-d depth: the widest dimension of the node, the
+    first one on ties (Procedure 3).  Nodes at one depth share their extents,
+    so the axis sequence depends on the depth only."""
+    ext = np.asarray(dom_hi, dtype=np.float64) - np.asarray(dom_lo, dtype=np.float64)
+    axes = []
+    for _ in range(depth):
+        a = int(np.argmax(ext))
+        axes.append(a)
+        ext[a] /= 2.0
+    return axes
+
+
+def kd_bounds(code, depth, dom_lo, dom_hi):
+    """Bounds of k-d nodes: ``code`` holds ``depth`` bits, the most significant
+    bit being the first split; bit 1 selects the upper half (the child
+    [x_l + x_s, x_u] with x_s half the width)."""
+    axes = kd_axes(depth, dom_lo, dom_hi)
+    code = np.asarray(code, dtype=np.uint64)
+    lo = np.tile(np.asarray(dom_lo, dtype=np.float64), (code.size, 1))
+    hi = np.tile(np.asarray(dom_hi, dtype=np.float64), (code.size, 1))
+    for d, a in enumerate(axes):
+        bit = ((code >> np.uint64(depth - 1 - d)) & np.uint64(1)).astype(bool)
+        mid = (lo[:, a] + hi[:, a]) / 2.0
+        lo[:, a] = np.where(bit, mid, lo[:, a])
+        hi[:, a] = np.where(bit, hi[:, a], mid)
+    return lo, hi
+
+
+def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1),
+                 arity=8, keep_leaf_lists=False, max_cells=None):
+    """Fixed-depth BuildSpatialTree in parallel rounds.
+
+    Each round classifies every cell of the current level: POSITIVE and
+    NEGATIVE cells become leaves; UNKNOWN cells below ``max_level`` are split
+    (arity 8: into 8 equal octants; arity 2: the widest dimension at its
+    midpoint); UNKNOWN cells at ``max_level`` form the leaf list handed to mesh
+    extraction.  Returns a dict with per-level frontier sizes and counts, the
+    sorted UNKNOWN leaf codes and (optionally) the POSITIVE/NEGATIVE leaves.
+    """
+    codes = np.zeros(1, dtype=np.uint64)
+    levels = []
+    pos_leaves, neg_leaves = [], []
+    unk_leaves = np.zeros(0, dtype=np.uint64)
+    for level in range(max_level + 1):
+        if arity == 8:
+            lo, hi = cell_bounds(codes, level, dom_lo, dom_hi)
+        else:
+            lo, hi = kd_bounds(codes, level, dom_lo, dom_hi)
+        if codes.size:
+            _, _, ly, hy = mlp.bound_boxes(net, lo, hi, policy, k)
+            lab = classify(ly, hy)
+        else:
+            lab = np.zeros(0, dtype=np.uint8)
+        unk = codes[lab == UNKNOWN]
+        levels.append({"level": level, "n": int(codes.size), "n_pos": int((lab == POSITIVE).sum()),
+                       "n_neg": int((lab == NEGATIVE).sum()), "n_unk": int(unk.size)})
+        if keep_leaf_lists:
+            pos_leaves.append((level, codes[lab == POSITIVE]))
+            neg_leaves.append((level, codes[lab == NEGATIVE]))
+        if level == max_level:
+            unk_leaves = np.sort(unk)
+            break
+        shift = np.uint64(3 if arity == 8 else 1)
+        kids = [(unk << shift) | np.uint64(o) for o in range(arity)]
+        codes = np.sort(np.concatenate(kids)) if unk.size else np.zeros(0, dtype=np.uint64)
+        if max_cells is not None and codes.size > max_cells:
+            raise RuntimeError("frontier exceeds max_cells")
+    return {"levels": levels, "leaves": unk_leaves, "pos": pos_leaves, "neg": neg_leaves}
+
+
+# ---------------------------------------------------------------------------
+# Ray casting (Procedure 2)
+# ---------------------------------------------------------------------------
+
+def clip_to_box(o, d, lo=-1.0, hi=1.0):
+    """Slab test: entry/exit parameters of the rays in the box; miss flag."""
+    o = np.asarray(o, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        t1 = (lo - o) * inv
+        t2 = (hi - o) * inv
+    tmin = np.minimum(t1, t2)
+    tmax = np.maximum(t1, t2)
+    # a zero direction component: inside the slab -> (-inf, inf), else empty
+    zero = d == 0.0
+    inside = (o >= lo) & (o <= hi)
+    tmin = np.where(zero, np.where(inside, -np.inf, np.inf), tmin)
+    tmax = np.where(zero, np.where(inside, np.inf, -np.inf), tmax)
+    t_in = np.maximum(np.max(tmin, axis=1), 0.0)
+    t_out = np.min(tmax, axis=1)
+    hit = t_out > t_in
+    return t_in, t_out, hit
+
+
+def different_signs(a, b):
+    """Sign change test: zero counts as inside (negative side)."""
+    return (np.asarray(a) > 0.0) != (np.asarray(b) > 0.0)
+
+
+def cast_rays(net, origin, direction, delta=1e-3, t_max=10.0, sigma0=None, eta_minus=0.5, eta_plus=1.5,
+              safety=0.98, max_iters=100000, clip_to_domain=True, policy="fixed", k=31):
+    """CastRay for a batch of rays, all advanced in lock-step rounds.
+
+    Per round for each active ray: evaluate f at t + delta and return t on a
+    sign change relative to f at the start; otherwise bound f on the segment
+    [t, t + sigma] and either accept the step (sigma* = safety sigma, sigma
+    grows by eta_plus) or reject it (sigma* = 0, sigma shrinks by eta_minus);
+    then t += max(sigma*, delta).  With ``clip_to_domain`` each ray is first
+    clipped to [-1,1]^3 and marched from its entry point over its chord only.
+
+    Returns (t_hit [n] with +inf for no hit, iterations [n])."""
+    o = np.asarray(origin, dtype=np.float64)
+    d = np.asarray(direction, dtype=np.float64)
+    n = o.shape[0]
+    if sigma0 is None:
+        sigma0 = t_max / 10.0
+    t_hit = np.full(n, np.inf)
+    iters = np.zeros(n, dtype=np.int64)
+    if clip_to_domain:
+        t_in, t_out, inside = clip_to_box(o, d)
+        start = o + t_in[:, None] * d
+        tmax_r = np.where(inside, t_out - t_in, 0.0)
+        base = t_in
+    else:
+        start = o.copy()
+        tmax_r = np.full(n, float(t_max))
+        base = np.zeros(n)
+        inside = np.ones(n, dtype=bool)
+    t = np.zeros(n)
+    sigma = np.full(n, float(sigma0))
+    active = inside & (tmax_r > 0.0)
+    f0 = np.zeros(n)
+    if np.any(active):
+        f0[active] = mlp.forward(net, start[active])
+    while np.any(active):
+        idx = np.flatnonzero(active)
+        still = t[idx] < tmax_r[idx]
+        active[idx[~still]] = False
+        idx = idx[still]
+        if idx.size == 0:
+            break
+        iters[idx] += 1
+        pc = start[idx] + (t[idx] + delta)[:, None] * d[idx]
+        fc = mlp.forward(net, pc)
+        hit = different_signs(f0[idx], fc)
+        t_hit[idx[hit]] = base[idx[hit]] + t[idx[hit]]
+        active[idx[hit]] = False
+        idx = idx[~hit]
+        if idx.size == 0:
+            continue
+        ly, hy = mlp.bound_segments(net, start[idx], d[idx], t[idx], sigma[idx], policy, k)
+        safe = classify(ly, hy) != UNKNOWN
+        step = np.where(safe, safety * sigma[idx], 0.0)
+        sigma[idx] = np.where(safe, sigma[idx] * eta_plus, sigma[idx] * eta_minus)
+        t[idx] = t[idx] + np.maximum(step, delta)
+        over = iters[idx] >= max_iters
+        active[idx[over]] = False
+    return t_hit, iters
+
+
+# ---------------------------------------------------------------------------
+# Closest point (Section 4.10)
+# ---------------------------------------------------------------------------
+
+def face_centers(lo, hi):
+    c = (lo + hi) / 2.0
+    pts = []
+    for a in range(3):
+        for v in (lo[a], hi[a]):
+            p = c.copy()
+            p[a] = v
+            pts.append(p)
+    return np.array(pts)
+
+
+def closest_point(net, q, max_level=8, policy="fixed", k=31, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1)):
+    """Lazy best-first descent of the octree for one query point q.
+
+    Cells are visited in order of their minimum distance to q.  A cell is
+    skipped when that distance is not below the best distance found, or when
+    RangeBound classifies it.  A cell whose six face-center samples show both
+    signs spans the level set: the best distance becomes at most the farthest
+    distance from q to the cell and its center becomes the candidate.  Cells
+    below ``max_level`` push their 8 children.
+
+    Returns (point [3], distance from q to the point, best bound); point is
+    None and the distances +inf if no cell spanning the surface was found."""
+    q = np.asarray(q, dtype=np.float64)
+    dom_lo = np.asarray(dom_lo, dtype=np.float64)
+    dom_hi = np.asarray(dom_hi, dtype=np.float64)
+
+    def mind(lo, hi):
+        return float(np.linalg.norm(np.maximum(np.maximum(lo - q, q - hi), 0.0)))
+
+    def maxd(lo, hi):
+        return float(np.linalg.norm(np.maximum(np.abs(q - lo), np.abs(q - hi))))
+
+    best = math.inf
+    point = None
+    heap = [(mind(dom_lo, dom_hi), 0, 0)]   # (min distance, level, code)
+    while heap:
+        dmin, level, code = heapq.heappop(heap)
+        if dmin >= best:
+            break
+        lo, hi = cell_bounds(np.array([code], dtype=np.uint64), level, dom_lo, dom_hi)
+        lo, hi = lo[0], hi[0]
+        _, _, ly, hy = mlp.bound_boxes(net, lo[None], hi[None], policy, k)
+        if classify(ly, hy)[0] != UNKNOWN:
+            continue
+        fv = mlp.forward(net, face_centers(lo, hi))
+        if np.any(fv < 0.0) and np.any(fv > 0.0):
+            dm = maxd(lo, hi)
+            if dm < best:
+                best = dm
+                point = (lo + hi) / 2.0
+        if level < max_level:
+            for o in range(8):
+                c2 = (code << 3) | o
+                l2, h2 = cell_bounds(np.array([c2], dtype=np.uint64), level + 1, dom_lo, dom_hi)
+                dm2 = mind(l2[0], h2[0])
+                if dm2 < best:
+                    heapq.heappush(heap, (dm2, level + 1, c2))
+    if point is None:
+        return None, math.inf, math.inf
+    return point, float(np.linalg.norm(point - q)), best

@@ -1,0 +1,172 @@
+"""Pins of the oracle's queries (Procedures 2 and 3, Section 4.10): closed-form
+ray hits, the octree's exact partition of the domain, closest points on an
+exactly representable octahedron (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp
+from oracle import queries as q
+
+
+def test_morton_roundtrip():
+    rng = np.random.default_rng(1)
+    for level in (0, 1, 5, 10, 21):
+        n = 1 << level
+        ix, iy, iz = (rng.integers(0, n, 100) for _ in range(3))
+        code = q.morton_encode(ix, iy, iz, level)
+        jx, jy, jz = q.morton_decode(code, level)
+        assert np.array_equal(ix, jx) and np.array_equal(iy, jy) and np.array_equal(iz, jz)
+    # children of a cell are (code << 3) | octant and tile the parent
+    lo, hi = q.cell_bounds(np.array([5], dtype=np.uint64), 2, (-1, -1, -1), (1, 1, 1))
+    kids = (np.uint64(5) << np.uint64(3)) | np.arange(8, dtype=np.uint64)
+    klo, khi = q.cell_bounds(kids, 3, (-1, -1, -1), (1, 1, 1))
+    assert np.allclose(klo.min(0), lo[0]) and np.allclose(khi.max(0), hi[0])
+    assert np.isclose(np.prod(khi - klo, axis=1).sum(), np.prod(hi - lo))
+
+
+def test_kd_bounds_split_widest_at_midpoint():
+    lo, hi = q.kd_bounds(np.array([0b1], dtype=np.uint64), 1, (-1, -2, -1), (1, 2, 1))
+    assert np.allclose(lo[0], [-1, 0, -1]) and np.allclose(hi[0], [1, 2, 1])   # y is widest
+    lo, hi = q.kd_bounds(np.array([0b10], dtype=np.uint64), 2, (-1, -1, -1), (1, 1, 1))
+    assert np.allclose(lo[0], [0, -1, -1]) and np.allclose(hi[0], [1, 0, 1])   # x then y
+
+
+def _tree_volume(res, dom=8.0, arity=8):
+    vol = 0.0
+    for level, codes in res["pos"] + res["neg"]:
+        vol += codes.size * dom / (arity ** level)
+    L = len(res["levels"]) - 1
+    vol += res["leaves"].size * dom / (arity ** L)
+    return vol
+
+
+@pytest.mark.parametrize("arity,depth", [(8, 5), (2, 12)])
+def test_octree_partition_and_soundness(arity, depth):
+    net = wl.tiny_net(0)
+    res = q.octree_build(net, depth, "truncate", 16, arity=arity, keep_leaf_lists=True)
+    assert _tree_volume(res, arity=arity) == 8.0          # exact: sizes are powers of two
+    rng = np.random.default_rng(2)
+    for (level, codes), sign in [(p, 1) for p in res["pos"]] + [(p, -1) for p in res["neg"]]:
+        if codes.size == 0:
+            continue
+        sel = codes[rng.integers(0, codes.size, min(codes.size, 40))]
+        lo, hi = (q.cell_bounds(sel, level, (-1,) * 3, (1,) * 3) if arity == 8
+                  else q.kd_bounds(sel, level, (-1,) * 3, (1,) * 3))
+        for b in range(sel.size):
+            P = lo[b] + rng.uniform(0, 1, (64, 3)) * (hi[b] - lo[b])
+            f = mlp.forward(net, P)
+            assert np.all(sign * f > 0)
+
+
+def test_octree_keeps_every_sampled_sign_change():
+    net = wl.tiny_net(0)
+    depth = 5
+    res = q.octree_build(net, depth, "truncate", 31)
+    leaves = set(int(c) for c in res["leaves"])
+    n = 1 << depth
+    rng = np.random.default_rng(3)
+    ix, iy, iz = (rng.integers(0, n, 3000) for _ in range(3))
+    codes = q.morton_encode(ix, iy, iz, depth)
+    lo, hi = q.cell_bounds(codes, depth, (-1,) * 3, (1,) * 3)
+    for b in range(codes.size):
+        t = np.linspace(0, 1, 4)
+        g = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+        f = mlp.forward(net, lo[b] + g * (hi[b] - lo[b]))
+        if f.min() < 0 < f.max():
+            assert int(codes[b]) in leaves
+
+
+def _plane_net(a, b, M=16.0):
+    a = np.asarray(a, dtype=np.float64)
+    W1 = a[None, :].astype(np.float32)
+    return wl.MLPSpec([W1, np.array([[1.0]], dtype=np.float32)],
+                      [np.array([b + M], dtype=np.float32), np.array([-M], dtype=np.float32)], act="relu")
+
+
+def test_cast_ray_plane_closed_form():
+    a = np.array([0.5, -0.25, 0.75], dtype=np.float32).astype(np.float64)
+    b = 0.125
+    net = _plane_net(a, b)
+    o, d = wl.camera_rays(16, 16, 4)
+    o = o.astype(np.float64)
+    d = d.astype(np.float64)
+    delta = 1e-3
+    th, it = q.cast_rays(net, o, d, delta=delta)
+    t_in, t_out, inside = q.clip_to_box(o, d)
+    fo = o @ a + b
+    ts = -fo / (d @ a)
+    exp_hit = inside & (ts >= t_in) & (ts <= t_out)
+    # a start exactly on the far side of the plane has no crossing along the chord
+    assert np.array_equal(np.isfinite(th), exp_hit)
+    hit = exp_hit
+    assert np.all(th[hit] <= ts[hit] + 1e-9) and np.all(th[hit] >= ts[hit] - delta - 1e-9)
+
+
+def _octahedron_first_hit(p, r, R, T):
+    """First root of g(t) = |p + t r|_1 - R on [0, T] (convex piecewise linear):
+    walk the breakpoints where a coordinate changes sign."""
+    bps = [0.0] + sorted(t for t in (-p / np.where(r == 0, np.inf, r)) if 0.0 < t < T) + [T]
+    g = lambda t: np.abs(p + t * r).sum() - R
+    for t0, t1 in zip(bps[:-1], bps[1:]):
+        g0, g1 = g(t0), g(t1)
+        if g0 == 0.0:
+            return t0
+        if (g0 > 0) != (g1 > 0):
+            return t0 + g0 * (t1 - t0) / (g0 - g1)
+    return math.inf
+
+
+def test_cast_ray_octahedron_closed_form():
+    R = 0.6
+    net = wl.octahedron_mlp(R)
+    o, d = wl.camera_rays(20, 20, 5, fov_deg=22.0)
+    o = o.astype(np.float64)
+    d = d.astype(np.float64)
+    delta = 1e-3
+    th, it = q.cast_rays(net, o, d, delta=delta)
+    t_in, t_out, inside = q.clip_to_box(o, d)
+    for i in range(o.shape[0]):
+        if not inside[i]:
+            assert math.isinf(th[i])
+            continue
+        p = o[i] + t_in[i] * d[i]
+        ts = _octahedron_first_hit(p, d[i], R, t_out[i] - t_in[i])
+        if math.isinf(ts):
+            assert math.isinf(th[i])
+        else:
+            ts += t_in[i]
+            assert ts - delta - 1e-9 <= th[i] <= ts + 1e-9, (i, th[i], ts)
+    assert np.isfinite(th).sum() > 50
+
+
+def _l1_ball_distance(x, R):
+    s = np.abs(x).sum()
+    if s <= R:
+        return (R - s) / math.sqrt(3.0)
+    u = np.sort(np.abs(x))[::-1]
+    cs = np.cumsum(u)
+    rho = max(j for j in range(1, 4) if u[j - 1] - (cs[j - 1] - R) / j > 0)
+    theta = (cs[rho - 1] - R) / rho
+    proj = np.maximum(np.abs(x) - theta, 0.0)
+    return float(np.linalg.norm(np.abs(x) - proj))
+
+
+def test_closest_point_octahedron():
+    # a radius off the dyadic grid: with R = 0.5 the surface passes exactly
+    # through cell face centers, where the sign test sees f = 0
+    net = wl.octahedron_mlp(0.55)
+    R = float(net.biases[1][0]) * -1.0
+    rng = np.random.default_rng(6)
+    L = 6
+    diag = math.sqrt(3.0) * 2.0 / (1 << L)
+    for _ in range(6):
+        x = rng.uniform(-1, 1, 3)
+        pt, dist, best = q.closest_point(net, x, max_level=L, policy="fixed")
+        dstar = _l1_ball_distance(x, R)
+        assert pt is not None
+        assert best >= dstar - 1e-12
+        assert dstar - diag / 2 - 1e-12 <= dist <= dstar + diag + 1e-12
+        assert abs(np.abs(pt).sum() - R) <= math.sqrt(3.0) * diag / 2 + 1e-12
