@@ -1,0 +1,200 @@
+/*
+ * spk.h -- C ABI of the MI355X range-analysis library.
+ *
+ * Guaranteed range bounds of an MLP implicit function f: R^3 -> R over many
+ * boxes, rays and cells at once, after Sharp & Jacobson, "Spelunking the Deep:
+ * Guaranteed Queries on General Neural Implicit Surfaces via Range Analysis"
+ * (ACM TOG 41(4), 2022):
+ *
+ *   spk_range_bound        RangeBound, Procedure 1, steps 1-3 (the bound)
+ *   spk_classify_boxes     RangeBound, Procedure 1, steps 1-6 (sign class)
+ *   spk_subdivide_frontier one parallel round of BuildSpatialTree,
+ *                          Procedure 3 / Section 4.5 (fixed depth, Section 4.7)
+ *   spk_cast_rays          CastRay, Procedure 2 (with the Appendix B step safety)
+ *
+ * Conventions shared by every call
+ *  - Every call returns an spk_status.  Nothing aborts or prints.
+ *  - Pointers documented "dev" are device (HBM) pointers allocated and owned by
+ *    the caller; "host" pointers are read during the call only.
+ *  - All work is enqueued asynchronously on the context's HIP stream.  The
+ *    returned status covers argument validation and launch errors; call
+ *    spk_ctx_sync to wait.  Arguments are validated before any HIP call.
+ *  - An spk_net is read-only after creation and may be shared by contexts.
+ *    One spk_ctx must not be used from two host threads at once.
+ *  - n == 0 is a no-op returning SPK_OK.
+ *  - Bounds are sound in floating point: the returned [lo, hi] contains f over
+ *    the whole region (the arithmetic is FP32 on MFMA and VALU, with a
+ *    rigorous rounding-error radius added).  Non-finite inputs give
+ *    lo = -inf, hi = +inf and label UNKNOWN.
+ */
+#ifndef SPK_H
+#define SPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPK_OK = 0,
+  SPK_E_INVAL = 1,        /* bad argument (null pointer, bad size or enum)        */
+  SPK_E_NOMEM = 2,        /* device or host allocation failed                     */
+  SPK_E_NOSPC = 3,        /* an output array is too small; see the call           */
+  SPK_E_DEVICE = 4,       /* a HIP runtime call failed                            */
+  SPK_E_UNSUPPORTED = 5,  /* valid request this build does not implement          */
+  SPK_E_BUSY = 6          /* object still in use                                  */
+} spk_status;
+
+/* Activations (Table 3).  SPK_ACT_SIN is sin(omega0 * z) (SIREN convention). */
+typedef enum { SPK_ACT_RELU = 0, SPK_ACT_ELU = 1, SPK_ACT_SIN = 2 } spk_act;
+
+/* Condensation policies (Section 3.3).  affine-full is not implemented on the
+ * GPU (SPK_E_UNSUPPORTED). */
+typedef enum { SPK_AFFINE_FIXED = 0, SPK_AFFINE_TRUNCATE = 1, SPK_AFFINE_FULL = 2 } spk_policy;
+
+/* Arithmetic of the generator products. */
+typedef enum { SPK_PREC_F32 = 0 } spk_prec;
+
+/* uint8 sign classes of Procedure 1. */
+enum { SPK_UNKNOWN = 0, SPK_POSITIVE = 1, SPK_NEGATIVE = 2 };
+
+typedef struct {
+  int32_t policy;   /* spk_policy                                                */
+  int32_t k;        /* affine-truncate: number of kept terms, 3 <= k <= 31       */
+  int32_t prec;     /* spk_prec                                                  */
+  uint32_t flags;   /* reserved, 0                                               */
+} spk_bound_opts;
+
+typedef struct spk_net spk_net;
+typedef struct spk_ctx spk_ctx;
+
+const char* spk_status_str(spk_status s);
+
+/* Library version string. */
+const char* spk_version(void);
+
+/*
+ * spk_net_create: upload an MLP (Section 2 setting): n_linear linear layers,
+ * the activation after every layer but the last.
+ *   widths  host [n_linear+1]: widths[0] = 3, widths[n_linear] = 1, all hidden
+ *           widths equal to one H in {32, 64, 128, 256}; n_linear in [2, 16].
+ *   W       host [n_linear] pointers, W[l] row-major [widths[l+1]][widths[l]].
+ *   b       host [n_linear] pointers, b[l] of length widths[l+1].
+ *   act     spk_act; omega0 the sine frequency (ignored unless SPK_ACT_SIN, > 0).
+ * The library copies everything into its own device buffers (on the current
+ * HIP device), precomputes the per-layer rounding constants in FP64 and owns
+ * the result until spk_net_destroy.  Returns SPK_E_UNSUPPORTED for shapes
+ * outside the list above.
+ */
+spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* const* W,
+                          const float* const* b, int32_t act, float omega0, spk_net** out);
+spk_status spk_net_destroy(spk_net* net);
+
+/*
+ * spk_ctx_create: a context bound to one HIP stream (a hipStream_t passed as
+ * void*; NULL is the default stream).  workspace_bytes is an upper bound on the
+ * scratch memory the context may allocate (0 = no limit).
+ */
+spk_status spk_ctx_create(void* stream, size_t workspace_bytes, spk_ctx** out);
+spk_status spk_ctx_destroy(spk_ctx* ctx);
+/* Wait for all work of the context's stream. */
+spk_status spk_ctx_sync(spk_ctx* ctx);
+
+/*
+ * Optional diagnostic outputs of the bound calls (all dev, nullable).
+ *   center, radius  [n]: the raw bound before rounding inflation,
+ *                   lo_raw = center - radius, hi_raw = center + radius.
+ *   err             [n]: rounding-error radius; lo <= center - radius - err.
+ *   slot_src        [(n_linear-2+1)][n][32] int16: for affine-truncate, after
+ *                   each activation (n_linear-1 of them) and for each of the
+ *                   32 term slots of each box: -1 the slot kept its previous
+ *                   term, j >= 0 it now holds the new term of neuron j, -2 the
+ *                   slot is empty.  Slot 0 is the center (always -1).
+ */
+typedef struct {
+  float* center;
+  float* radius;
+  float* err;
+  int16_t* slot_src;
+} spk_bound_aux;
+
+/*
+ * spk_range_bound: Procedure 1, steps 1-3 for general boxes.
+ *   n       number of boxes; s in {1, 2, 3} box axes per box.
+ *   center  dev [n][3]; axes dev [n][s][3] (half-axis vectors, need not be
+ *           axis-aligned; the box is center + sum_i eps_i axes[i], |eps_i| <= 1).
+ *   lo, hi  dev [n] outputs: a sound enclosure of f over each box.
+ *   aux     nullable, see spk_bound_aux.
+ */
+spk_status spk_range_bound(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n,
+                           int32_t s, const float* center, const float* axes, float* lo, float* hi,
+                           const spk_bound_aux* aux);
+
+/*
+ * spk_classify_boxes: Procedure 1 for axis-aligned boxes [box_lo, box_hi]
+ * (dev [n][3] each).  label dev [n] (uint8 SPK_UNKNOWN/POSITIVE/NEGATIVE:
+ * POSITIVE iff lo > 0, NEGATIVE iff hi < 0).  lo, hi dev [n] nullable.
+ */
+spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n,
+                              const float* box_lo, const float* box_hi, uint8_t* label, float* lo,
+                              float* hi, const spk_bound_aux* aux);
+
+/* Tree parameters: the domain box and the fixed maximum octree level. */
+typedef struct {
+  float dom_lo[3];
+  float dom_hi[3];
+  int32_t max_level;   /* 0 <= max_level <= 20                                   */
+  int32_t arity;       /* 8 (octree); other values give SPK_E_UNSUPPORTED        */
+} spk_tree_params;
+
+/*
+ * spk_subdivide_frontier: one parallel round of Procedure 3 at fixed depth.
+ * cells dev [n] are Morton codes at `level` (bit b of the x index at bit 3b,
+ * y at 3b+1, z at 3b+2).  Each cell is classified; POSITIVE and NEGATIVE cells
+ * are counted; UNKNOWN cells with level < max_level write their 8 children
+ * (code << 3 | octant) to `children`; UNKNOWN cells at max_level are copied to
+ * `leaves` (the cells handed to mesh extraction, Section 4.7).
+ *   children dev [cap_children], leaves dev [cap_leaves] (either may be NULL
+ *            when its capacity is 0).
+ *   counts   dev int64 [4]: n_children, n_leaves, n_pos, n_neg.  The call sets
+ *            them (it does not accumulate).  Output order is unspecified.
+ * When a capacity is too small the required count is still written to
+ * `counts`, entries beyond the capacity are dropped, and spk_ctx_sync returns
+ * nothing special: the caller compares counts with the capacities.
+ */
+spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                                  const spk_tree_params* tree, int32_t level, const uint64_t* cells,
+                                  int64_t n, uint64_t* children, int64_t cap_children, uint64_t* leaves,
+                                  int64_t cap_leaves, int64_t* counts);
+
+/* CastRay parameters (Procedure 2; Section 4.1 delta; Appendix B safety). */
+typedef struct {
+  float delta;          /* convergence length, e.g. 1e-3                            */
+  float t_max;          /* miss distance when clip_to_domain == 0                   */
+  float sigma0;         /* initial step, e.g. t_max / 10                            */
+  float eta_minus;      /* step shrink factor, e.g. 0.5                             */
+  float eta_plus;       /* step growth factor, e.g. 1.5                             */
+  float safety;         /* accepted step fraction, e.g. 0.98                        */
+  int32_t max_iters;    /* per-ray iteration cap (> 0)                              */
+  int32_t clip_to_domain; /* 1: march each ray over its chord of [-1,1]^3 only     */
+} spk_ray_params;
+
+/*
+ * spk_cast_rays: Procedure 2 for n rays (origin, dir dev [n][3]; dir unit
+ * length).  Segment bounds use affine-fixed (the paper's ray-casting choice).
+ *   t_hit  dev [n]: first t with a sign change within delta, +inf for no hit.
+ *   iters  dev int32 [n] nullable: loop iterations per ray.
+ */
+spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params* params, int64_t n,
+                         const float* origin, const float* dir, float* t_hit, int32_t* iters);
+
+/* Point evaluation f(x) for x dev [n][3] -> f dev [n] (FP32). */
+spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPK_H */

@@ -88,7 +88,7 @@ def matmul(x0, X, xinf, A):
     """z = A x: z0 = A x0, Z = A X, zinf = |A| xinf (|A| element-wise)."""
     A = np.asarray(A, dtype=np.float64)
     z0 = x0 @ A.T
-    Z = np.einsum("jk,bkn->bjn", A, X)
+    Z = np.matmul(A, X)
     zinf = xinf @ np.abs(A).T
     return z0, Z, zinf
 

@@ -1,0 +1,347 @@
+// C ABI of the library: argument validation, the device network store and
+// the launch sequence of every entry point.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "spk_impl.h"
+
+using namespace spk;
+
+namespace {
+
+// Round a non-negative double up to a float that is >= it.
+float up_f32(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+// Relative rounding constant of an n-term FP32 dot product plus a bias term,
+// with every multiply and add faithfully rounded (error <= 2^-23 relative),
+// in any accumulation order: gamma = m u' / (1 - m u'), m = n + 2, u' = 2^-23.
+double dot_const(int n, int mantissa_bits) {
+  const double up = ldexp(1.0, -(mantissa_bits - 1));
+  const double m = (double)n + 2.0;
+  return m * up / (1.0 - m * up) * (1.0 + 1e-6);
+}
+
+bool finite_all(const float* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(p[i])) return false;
+  return true;
+}
+
+spk_status check_hip(hipError_t e) { return e == hipSuccess ? SPK_OK : SPK_E_DEVICE; }
+
+spk_status valid_opts(const spk_bound_opts* o) {
+  if (o == nullptr) return SPK_E_INVAL;
+  if (o->prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;
+  if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
+  if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
+  if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;
+  return SPK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spk_status_str(spk_status s) {
+  switch (s) {
+    case SPK_OK: return "ok";
+    case SPK_E_INVAL: return "invalid argument";
+    case SPK_E_NOMEM: return "out of memory";
+    case SPK_E_NOSPC: return "output capacity too small";
+    case SPK_E_DEVICE: return "HIP runtime error";
+    case SPK_E_UNSUPPORTED: return "unsupported by this build";
+    case SPK_E_BUSY: return "object busy";
+  }
+  return "unknown status";
+}
+
+const char* spk_version(void) { return "spk 0.1 gfx950"; }
+
+spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* const* W, const float* const* b,
+                          int32_t act, float omega0, spk_net** out) {
+  if (out == nullptr || widths == nullptr || W == nullptr || b == nullptr) return SPK_E_INVAL;
+  *out = nullptr;
+  if (n_linear < 2 || n_linear > 16) return SPK_E_UNSUPPORTED;
+  if (act != SPK_ACT_RELU && act != SPK_ACT_ELU && act != SPK_ACT_SIN) return SPK_E_INVAL;
+  if (act == SPK_ACT_SIN && !(omega0 > 0.0f && isfinite(omega0))) return SPK_E_INVAL;
+  if (widths[0] != 3 || widths[n_linear] != 1) return SPK_E_UNSUPPORTED;
+  const int H = widths[1];
+  if (H != 32 && H != 64 && H != 128 && H != 256) return SPK_E_UNSUPPORTED;
+  for (int l = 1; l < n_linear; ++l)
+    if (widths[l] != H) return SPK_E_UNSUPPORTED;
+  for (int l = 0; l < n_linear; ++l) {
+    if (W[l] == nullptr || b[l] == nullptr) return SPK_E_INVAL;
+    if (!finite_all(W[l], (size_t)widths[l] * widths[l + 1]) || !finite_all(b[l], (size_t)widths[l + 1]))
+      return SPK_E_INVAL;
+  }
+  const int L = n_linear;
+  const double cK = dot_const(H, 24);
+  const double cD = dot_const(H, 53);
+  const double c3 = dot_const(3, 24);
+  const double eta = ldexp(1.0, -100);
+
+  // host images of every device array
+  const size_t nW0 = (size_t)H * 4, nb0 = H, nWp = (size_t)(L - 2) * H * H, nbh = (size_t)(L - 2) * H;
+  std::vector<float> W0(nW0, 0.0f), b0(nb0), Wp(nWp), bh(nbh), ebh(nbh), wL(H);
+  for (int r = 0; r < H; ++r) {
+    for (int d = 0; d < 3; ++d) W0[(size_t)r * 4 + d] = W[0][(size_t)r * 3 + d];
+    b0[r] = b[0][r];
+  }
+  const int MT = H / 16;
+  for (int l = 1; l <= L - 2; ++l) {
+    const float* Wl = W[l];
+    float* dst = Wp.data() + (size_t)(l - 1) * H * H;
+    // A-fragment order: [t][tp][lane][j] = W[16 tp + c][16 t + 4 g + j], lane = 16 g + c
+    for (int t = 0; t < MT; ++t)
+      for (int tp = 0; tp < MT; ++tp)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int j = 0; j < 4; ++j) {
+            const int g = lane >> 4, c = lane & 15;
+            const int row = 16 * tp + c, col = 16 * t + 4 * g + j;
+            dst[(((size_t)t * MT + tp) * 64 + lane) * 4 + j] = Wl[(size_t)row * H + col];
+          }
+    for (int r = 0; r < H; ++r) {
+      const float bv = b[l][r];
+      bh[(size_t)(l - 1) * H + r] = bv;
+      ebh[(size_t)(l - 1) * H + r] = up_f32(cK * fabs((double)bv) + eta);
+    }
+  }
+  for (int r = 0; r < H; ++r) wL[r] = W[L - 1][r];
+  const float bL = b[L - 1][0];
+
+  // one device block, 256-byte aligned pieces
+  auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+  const size_t oW0 = 0, ob0 = oW0 + al(nW0 * 4), oWp = ob0 + al(nb0 * 4), obh = oWp + al(nWp * 4 + 4),
+               oebh = obh + al(nbh * 4 + 4), owL = oebh + al(nbh * 4 + 4), total = owL + al((size_t)H * 4);
+  std::vector<unsigned char> img(total, 0);
+  memcpy(img.data() + oW0, W0.data(), nW0 * 4);
+  memcpy(img.data() + ob0, b0.data(), nb0 * 4);
+  if (nWp) memcpy(img.data() + oWp, Wp.data(), nWp * 4);
+  if (nbh) {
+    memcpy(img.data() + obh, bh.data(), nbh * 4);
+    memcpy(img.data() + oebh, ebh.data(), nbh * 4);
+  }
+  memcpy(img.data() + owL, wL.data(), (size_t)H * 4);
+
+  spk_net* net = new (std::nothrow) spk_net();
+  if (net == nullptr) return SPK_E_NOMEM;
+  if (hipGetDevice(&net->device) != hipSuccess) { delete net; return SPK_E_DEVICE; }
+  void* blk = nullptr;
+  if (hipMalloc(&blk, total) != hipSuccess) { delete net; return SPK_E_NOMEM; }
+  if (hipMemcpy(blk, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(blk);
+    delete net;
+    return SPK_E_DEVICE;
+  }
+  unsigned char* base = (unsigned char*)blk;
+  NetDev& d = net->dev;
+  d.L = L;
+  d.H = H;
+  d.act = act;
+  d.omega0 = act == SPK_ACT_SIN ? omega0 : 1.0f;
+  d.cK = up_f32(cK);
+  d.cD = up_f32(cD);
+  d.c3 = up_f32(c3);
+  d.eL = up_f32(cK * fabs((double)bL) + eta);
+  d.bL = bL;
+  d.W0 = (const float*)(base + oW0);
+  d.b0 = (const float*)(base + ob0);
+  d.Wp = (const float*)(base + oWp);
+  d.bh = (const float*)(base + obh);
+  d.ebh = (const float*)(base + oebh);
+  d.wL = (const float*)(base + owL);
+  net->dev_block = blk;
+  net->n_linear = n_linear;
+  net->width = H;
+  *out = net;
+  return SPK_OK;
+}
+
+spk_status spk_net_destroy(spk_net* net) {
+  if (net == nullptr) return SPK_E_INVAL;
+  spk_status st = SPK_OK;
+  if (net->dev_block) st = check_hip(hipFree(net->dev_block));
+  delete net;
+  return st;
+}
+
+spk_status spk_ctx_create(void* stream, size_t workspace_bytes, spk_ctx** out) {
+  if (out == nullptr) return SPK_E_INVAL;
+  *out = nullptr;
+  spk_ctx* ctx = new (std::nothrow) spk_ctx();
+  if (ctx == nullptr) return SPK_E_NOMEM;
+  ctx->stream = (hipStream_t)stream;
+  ctx->workspace_limit = workspace_bytes;
+  ctx->scratch = nullptr;
+  ctx->scratch_bytes = 0;
+  if (hipGetDevice(&ctx->device) != hipSuccess ||
+      hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
+    delete ctx;
+    return SPK_E_DEVICE;
+  }
+  *out = ctx;
+  return SPK_OK;
+}
+
+spk_status spk_ctx_destroy(spk_ctx* ctx) {
+  if (ctx == nullptr) return SPK_E_INVAL;
+  spk_status st = SPK_OK;
+  if (ctx->scratch) {
+    st = check_hip(hipStreamSynchronize(ctx->stream));
+    if (hipFree(ctx->scratch) != hipSuccess) st = SPK_E_DEVICE;
+  }
+  delete ctx;
+  return st;
+}
+
+spk_status spk_ctx_sync(spk_ctx* ctx) {
+  if (ctx == nullptr) return SPK_E_INVAL;
+  return check_hip(hipStreamSynchronize(ctx->stream));
+}
+
+static spk_status ctx_scratch(spk_ctx* ctx, size_t bytes, void** p) {
+  if (bytes > ctx->scratch_bytes) {
+    if (ctx->workspace_limit && bytes > ctx->workspace_limit) return SPK_E_NOMEM;
+    if (ctx->scratch) {
+      if (hipStreamSynchronize(ctx->stream) != hipSuccess) return SPK_E_DEVICE;
+      hipFree(ctx->scratch);
+      ctx->scratch = nullptr;
+      ctx->scratch_bytes = 0;
+    }
+    const size_t sz = (bytes + 4095) & ~(size_t)4095;
+    if (hipMalloc(&ctx->scratch, sz) != hipSuccess) return SPK_E_NOMEM;
+    ctx->scratch_bytes = sz;
+  }
+  *p = ctx->scratch;
+  return SPK_OK;
+}
+
+static void fill_aux(BoundJob& job, const spk_bound_aux* aux) {
+  if (aux) {
+    job.center = aux->center;
+    job.radius = aux->radius;
+    job.err = aux->err;
+    job.slot_src = aux->slot_src;
+  }
+}
+
+spk_status spk_range_bound(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n, int32_t s,
+                           const float* center, const float* axes, float* lo, float* hi, const spk_bound_aux* aux) {
+  if (ctx == nullptr || net == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
+  if (st != SPK_OK) return st;
+  if (n < 0 || s < 1 || s > 3) return SPK_E_INVAL;
+  if (n == 0) return SPK_OK;
+  if (center == nullptr || axes == nullptr || lo == nullptr || hi == nullptr) return SPK_E_INVAL;
+  if (aux && aux->slot_src && opts->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
+  BoundJob job = {};
+  job.n = n;
+  job.mode = IN_GENERAL;
+  job.s = s;
+  job.policy = opts->policy;
+  job.k = opts->k;
+  job.a = center;
+  job.b = axes;
+  job.lo = lo;
+  job.hi = hi;
+  fill_aux(job, aux);
+  return launch_bound(net, job, ctx->stream, ctx->num_cus);
+}
+
+spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n,
+                              const float* box_lo, const float* box_hi, uint8_t* label, float* lo, float* hi,
+                              const spk_bound_aux* aux) {
+  if (ctx == nullptr || net == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
+  if (st != SPK_OK) return st;
+  if (n < 0) return SPK_E_INVAL;
+  if (n == 0) return SPK_OK;
+  if (box_lo == nullptr || box_hi == nullptr || label == nullptr) return SPK_E_INVAL;
+  if (aux && aux->slot_src && opts->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
+  BoundJob job = {};
+  job.n = n;
+  job.mode = IN_AABB;
+  job.s = 3;
+  job.policy = opts->policy;
+  job.k = opts->k;
+  job.a = box_lo;
+  job.b = box_hi;
+  job.lo = lo;
+  job.hi = hi;
+  job.label = label;
+  fill_aux(job, aux);
+  return launch_bound(net, job, ctx->stream, ctx->num_cus);
+}
+
+spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                                  const spk_tree_params* tree, int32_t level, const uint64_t* cells, int64_t n,
+                                  uint64_t* children, int64_t cap_children, uint64_t* leaves, int64_t cap_leaves,
+                                  int64_t* counts) {
+  if (ctx == nullptr || net == nullptr || tree == nullptr || counts == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
+  if (st != SPK_OK) return st;
+  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
+  if (tree->max_level < 0 || tree->max_level > 20 || level < 0 || level > tree->max_level) return SPK_E_INVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
+      return SPK_E_INVAL;
+  if (n < 0 || cap_children < 0 || cap_leaves < 0) return SPK_E_INVAL;
+  if (n > 0 && cells == nullptr) return SPK_E_INVAL;
+  if ((cap_children > 0 && children == nullptr) || (cap_leaves > 0 && leaves == nullptr)) return SPK_E_INVAL;
+  void* scratch = nullptr;
+  if (n > 0) {
+    st = ctx_scratch(ctx, (size_t)n, &scratch);
+    if (st != SPK_OK) return st;
+  }
+  BoundJob job = {};
+  job.n = n;
+  job.mode = IN_CELL;
+  job.s = 3;
+  job.policy = opts->policy;
+  job.k = opts->k;
+  job.cells = cells;
+  job.level = level;
+  for (int d = 0; d < 3; ++d) {
+    job.dom_lo[d] = tree->dom_lo[d];
+    job.dom_hi[d] = tree->dom_hi[d];
+  }
+  job.label = (uint8_t*)scratch;
+  if (n > 0) {
+    st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+  }
+  return launch_compact((const uint8_t*)scratch, cells, n, level == tree->max_level, children, cap_children, leaves,
+                        cap_leaves, counts, ctx->stream, ctx->num_cus);
+}
+
+spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params* params, int64_t n,
+                         const float* origin, const float* dir, float* t_hit, int32_t* iters) {
+  if (ctx == nullptr || net == nullptr || params == nullptr) return SPK_E_INVAL;
+  if (n < 0) return SPK_E_INVAL;
+  const spk_ray_params& p = *params;
+  if (!(p.delta > 0.0f) || !(p.sigma0 > 0.0f) || !(p.eta_minus > 0.0f && p.eta_minus < 1.0f) ||
+      !(p.eta_plus >= 1.0f) || !(p.safety > 0.0f && p.safety <= 1.0f) || p.max_iters <= 0 ||
+      !isfinite(p.delta) || !isfinite(p.sigma0) || !isfinite(p.eta_plus))
+    return SPK_E_INVAL;
+  if (!p.clip_to_domain && !(p.t_max > 0.0f && isfinite(p.t_max))) return SPK_E_INVAL;
+  if (n == 0) return SPK_OK;
+  if (origin == nullptr || dir == nullptr || t_hit == nullptr) return SPK_E_INVAL;
+  return launch_rays(net, p, n, origin, dir, t_hit, iters, ctx->stream, ctx->num_cus);
+}
+
+spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f) {
+  if (ctx == nullptr || net == nullptr || n < 0) return SPK_E_INVAL;
+  if (n == 0) return SPK_OK;
+  if (x == nullptr || f == nullptr) return SPK_E_INVAL;
+  return launch_eval(net, n, x, f, ctx->stream, ctx->num_cus);
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal definitions shared by the HIP sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spk.h"
+
+namespace spk {
+
+// Device copy of a network (uploaded once by spk_net_create).
+//
+// Layer 0 (3 -> H) is applied on VALU; hidden layers 1..L-2 (H -> H) on MFMA
+// (generators, FP32) with the center column on VALU in FP64; the output layer
+// (H -> 1) on VALU.  For sine networks each hidden pre-activation is scaled
+// by omega0 (Table 2 constant multiplication) before sin.
+struct NetDev {
+  int L;             // number of linear layers (>= 2)
+  int H;             // hidden width
+  int act;           // spk_act
+  float omega0;      // sine frequency (1 for other activations)
+  float cK;          // relative rounding bound of an FP32 H-term dot product (+ bias), any order
+  float cD;          // the same for an FP64 H-term dot product
+  float c3;          // FP32 3-term dot product (layer 0 generators)
+  float eL;          // cK * |b_out| + absolute slack, rounded up
+  float bL;          // output bias
+  const float* W0;   // [H][4]: layer-0 rows padded to 4 floats
+  const float* b0;   // [H]
+  const float* Wp;   // (L-2) hidden layers, each H*H floats in MFMA A-fragment order
+  const float* bh;   // (L-2) * H biases
+  const float* ebh;  // (L-2) * H : cK * |b| + absolute slack, rounded up
+  const float* wL;   // [H] output weights
+};
+
+// Input of a bound launch: which box source feeds the first layer.
+enum InputMode { IN_AABB = 0, IN_GENERAL = 1, IN_CELL = 2 };
+
+struct BoundJob {
+  int64_t n;
+  int mode;           // InputMode
+  int s;              // number of box axes (1..3)
+  int policy;         // spk_policy (fixed or truncate)
+  int k;              // kept terms (truncate)
+  // IN_AABB: a = lo [n][3], b = hi [n][3]; IN_GENERAL: a = center [n][3], b = axes [n][s][3]
+  const float* a;
+  const float* b;
+  // IN_CELL
+  const uint64_t* cells;
+  int level;
+  float dom_lo[3];
+  float dom_hi[3];
+  // outputs (each nullable)
+  float* lo;
+  float* hi;
+  uint8_t* label;
+  float* center;
+  float* radius;
+  float* err;
+  int16_t* slot_src;
+};
+
+}  // namespace spk
+
+struct spk_net {
+  spk::NetDev dev;
+  void* dev_block;   // single device allocation holding every array of dev
+  int device;
+  int32_t n_linear;
+  int32_t width;
+};
+
+struct spk_ctx {
+  hipStream_t stream;
+  size_t workspace_limit;
+  int device;
+  int num_cus;
+  // scratch (grown on demand)
+  void* scratch;
+  size_t scratch_bytes;
+};
+
+namespace spk {
+// Launch helpers implemented in bound.hip / tree.hip / rays.hip.
+spk_status launch_bound(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus);
+spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t n, bool at_max,
+                          uint64_t* children, int64_t cap_children, uint64_t* leaves, int64_t cap_leaves,
+                          int64_t* counts, hipStream_t stream, int num_cus);
+spk_status launch_eval(const spk_net* net, int64_t n, const float* x, float* f, hipStream_t stream,
+                       int num_cus);
+spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, const float* origin,
+                       const float* dir, float* t_hit, int32_t* iters, hipStream_t stream, int num_cus);
+}  // namespace spk

@@ -1,0 +1,68 @@
+// Frontier compaction of one BuildSpatialTree round (Procedure 3 run in
+// parallel rounds, Section 4.5): UNKNOWN cells below the maximum level emit
+// their 8 children, UNKNOWN cells at the maximum level go to the leaf list,
+// POSITIVE/NEGATIVE cells are counted.  Wave-level ballot + prefix count, one
+// atomic per wave and output list.
+#include "spk_impl.h"
+
+namespace spk {
+
+__global__ void zero_counts_kernel(unsigned long long* counts) {
+  if (threadIdx.x < 4) counts[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict__ labels,
+                                                      const uint64_t* __restrict__ cells, int64_t n, int at_max,
+                                                      uint64_t* __restrict__ children, int64_t cap_children,
+                                                      uint64_t* __restrict__ leaves, int64_t cap_leaves,
+                                                      unsigned long long* counts) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+    const int64_t i = base + lane;
+    const bool in = i < n;
+    const uint8_t lab = in ? labels[i] : (uint8_t)255;
+    const bool unk = lab == SPK_UNKNOWN;
+    const unsigned long long mu = __ballot(unk);
+    const unsigned long long mp = __ballot(lab == SPK_POSITIVE);
+    const unsigned long long mn = __ballot(lab == SPK_NEGATIVE);
+    const int nu = __popcll(mu);
+    unsigned long long off = 0ull;
+    if (lane == 0) {
+      if (nu) off = atomicAdd(&counts[at_max ? 1 : 0], (unsigned long long)(at_max ? nu : 8 * nu));
+      if (mp) atomicAdd(&counts[2], (unsigned long long)__popcll(mp));
+      if (mn) atomicAdd(&counts[3], (unsigned long long)__popcll(mn));
+    }
+    off = __shfl(off, 0, 64);
+    if (unk) {
+      const int64_t pre = __popcll(mu & below);
+      const uint64_t code = cells[i];
+      if (at_max) {
+        const int64_t p = (int64_t)off + pre;
+        if (p < cap_leaves) leaves[p] = code;
+      } else {
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+          const int64_t p = (int64_t)off + 8 * pre + o;
+          if (p < cap_children) children[p] = (code << 3) | (uint64_t)o;
+        }
+      }
+    }
+  }
+}
+
+spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t n, bool at_max, uint64_t* children,
+                          int64_t cap_children, uint64_t* leaves, int64_t cap_leaves, int64_t* counts,
+                          hipStream_t stream, int num_cus) {
+  hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, stream, (unsigned long long*)counts);
+  if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
+  if (n <= 0) return SPK_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)num_cus * 8) blocks = (int64_t)num_cus * 8;
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, labels, cells, n, at_max ? 1 : 0,
+                     children, cap_children, leaves, cap_leaves, (unsigned long long*)counts);
+  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+}
+
+}  // namespace spk

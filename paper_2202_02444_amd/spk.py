@@ -1,0 +1,282 @@
+"""Thin ctypes binding of the C ABI declared in ``include/spk.h``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch tensors on the GPU (torch supplies memory
+and the stream); the library never sees torch types.  If ``libspk.so`` is
+missing the first call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspk.so")
+
+OK, E_INVAL, E_NOMEM, E_NOSPC, E_DEVICE, E_UNSUPPORTED, E_BUSY = range(7)
+ACT = {"relu": 0, "elu": 1, "sin": 2}
+POLICY = {"fixed": 0, "truncate": 1, "full": 2}
+UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
+
+EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
+           "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
+           "spk_subdivide_frontier", "spk_cast_rays", "spk_eval_points")
+
+
+class BoundOpts(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("k", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class BoundAux(ctypes.Structure):
+    _fields_ = [("center", ctypes.c_void_p), ("radius", ctypes.c_void_p), ("err", ctypes.c_void_p),
+                ("slot_src", ctypes.c_void_p)]
+
+
+class TreeParams(ctypes.Structure):
+    _fields_ = [("dom_lo", ctypes.c_float * 3), ("dom_hi", ctypes.c_float * 3), ("max_level", ctypes.c_int32),
+                ("arity", ctypes.c_int32)]
+
+
+class RayParams(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_float), ("t_max", ctypes.c_float), ("sigma0", ctypes.c_float),
+                ("eta_minus", ctypes.c_float), ("eta_plus", ctypes.c_float), ("safety", ctypes.c_float),
+                ("max_iters", ctypes.c_int32), ("clip_to_domain", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libspk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libspk.so is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.spk_status_str.restype = ctypes.c_char_p
+        L.spk_status_str.argtypes = [ctypes.c_int]
+        L.spk_version.restype = ctypes.c_char_p
+        L.spk_version.argtypes = []
+        L.spk_net_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
+                                     ctypes.c_float, ctypes.POINTER(vp)]
+        L.spk_net_destroy.argtypes = [vp]
+        L.spk_ctx_create.argtypes = [vp, sz, ctypes.POINTER(vp)]
+        L.spk_ctx_destroy.argtypes = [vp]
+        L.spk_ctx_sync.argtypes = [vp]
+        L.spk_range_bound.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, i32, vp, vp, vp, vp,
+                                      ctypes.POINTER(BoundAux)]
+        L.spk_classify_boxes.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, vp, vp, vp, vp, vp,
+                                         ctypes.POINTER(BoundAux)]
+        L.spk_subdivide_frontier.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
+                                             i64, vp, i64, vp, i64, vp]
+        L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
+        L.spk_eval_points.argtypes = [vp, vp, i64, vp, vp]
+        for name in EXPORTS:
+            if name not in ("spk_status_str", "spk_version"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class SpkError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (where, lib().spk_status_str(status).decode(), status))
+
+
+def _check(st, where):
+    if st != OK:
+        raise SpkError(st, where)
+
+
+def _ptr(t, dtype=None, shape=None, name="tensor"):
+    """Device pointer of a contiguous torch CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s" % (name, dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def opts(policy="truncate", k=31):
+    return BoundOpts(POLICY[policy], int(k), 0, 0)
+
+
+class Net:
+    """A network uploaded to the current HIP device (spk_net_create)."""
+
+    def __init__(self, weights, biases, act="relu", omega0=1.0):
+        L = lib()
+        Ws = [np.ascontiguousarray(np.asarray(w, dtype=np.float32)) for w in weights]
+        bs = [np.ascontiguousarray(np.asarray(b, dtype=np.float32).reshape(-1)) for b in biases]
+        widths = [Ws[0].shape[1]] + [w.shape[0] for w in Ws]
+        n = len(Ws)
+        wa = (ctypes.c_int32 * (n + 1))(*widths)
+        Wp = (ctypes.c_void_p * n)(*[w.ctypes.data for w in Ws])
+        bp = (ctypes.c_void_p * n)(*[b.ctypes.data for b in bs])
+        h = ctypes.c_void_p()
+        _check(L.spk_net_create(n, wa, Wp, bp, ACT[act], float(omega0), ctypes.byref(h)), "spk_net_create")
+        self._keep = (Ws, bs)
+        self.handle = h
+        self.n_linear = n
+        self.width = widths[1]
+        self.act = act
+
+    @classmethod
+    def from_spec(cls, spec):
+        return cls(spec.weights, spec.biases, spec.act, spec.omega0)
+
+    def close(self):
+        if self.handle:
+            _check(lib().spk_net_destroy(self.handle), "spk_net_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A context on a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None, workspace_bytes=0):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib().spk_ctx_create(ctypes.c_void_p(stream), workspace_bytes, ctypes.byref(h)), "spk_ctx_create")
+        self.handle = h
+
+    def sync(self):
+        _check(lib().spk_ctx_sync(self.handle), "spk_ctx_sync")
+
+    def close(self):
+        if self.handle:
+            _check(lib().spk_ctx_destroy(self.handle), "spk_ctx_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _aux(center=None, radius=None, err=None, slot_src=None):
+    import torch
+    if center is None and radius is None and err is None and slot_src is None:
+        return None
+    return BoundAux(_ptr(center, torch.float32, name="center"), _ptr(radius, torch.float32, name="radius"),
+                    _ptr(err, torch.float32, name="err"), _ptr(slot_src, torch.int16, name="slot_src"))
+
+
+def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="truncate", k=31, aux=None):
+    import torch
+    n = box_lo.shape[0]
+    o = opts(policy, k)
+    a = _aux(**aux) if aux else None
+    st = lib().spk_classify_boxes(ctx.handle, net.handle, ctypes.byref(o), n,
+                                  _ptr(box_lo, torch.float32, (n, 3), "box_lo"),
+                                  _ptr(box_hi, torch.float32, (n, 3), "box_hi"),
+                                  _ptr(label, torch.uint8, (n,), "label"),
+                                  _ptr(lo, torch.float32, (n,), "lo"), _ptr(hi, torch.float32, (n,), "hi"),
+                                  ctypes.byref(a) if a is not None else None)
+    _check(st, "spk_classify_boxes")
+
+
+def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=None):
+    import torch
+    n, s = axes.shape[0], axes.shape[1]
+    o = opts(policy, k)
+    a = _aux(**aux) if aux else None
+    st = lib().spk_range_bound(ctx.handle, net.handle, ctypes.byref(o), n, s,
+                               _ptr(center, torch.float32, (n, 3), "center"),
+                               _ptr(axes, torch.float32, (n, s, 3), "axes"),
+                               _ptr(lo, torch.float32, (n,), "lo"), _ptr(hi, torch.float32, (n,), "hi"),
+                               ctypes.byref(a) if a is not None else None)
+    _check(st, "spk_range_bound")
+
+
+def subdivide_frontier(ctx, net, level, cells, children, leaves, counts, max_level, policy="truncate", k=31,
+                       dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8):
+    import torch
+    tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), int(arity))
+    o = opts(policy, k)
+    n = cells.shape[0]
+    capc = children.shape[0] if children is not None else 0
+    capl = leaves.shape[0] if leaves is not None else 0
+    st = lib().spk_subdivide_frontier(ctx.handle, net.handle, ctypes.byref(o), ctypes.byref(tp), int(level),
+                                      _ptr(cells, torch.int64, (n,), "cells"), n,
+                                      _ptr(children, torch.int64, None, "children"), capc,
+                                      _ptr(leaves, torch.int64, None, "leaves"), capl,
+                                      _ptr(counts, torch.int64, (4,), "counts"))
+    _check(st, "spk_subdivide_frontier")
+
+
+def ray_params(delta=1e-3, t_max=10.0, sigma0=None, eta_minus=0.5, eta_plus=1.5, safety=0.98, max_iters=100000,
+               clip_to_domain=True):
+    if sigma0 is None:
+        sigma0 = t_max / 10.0
+    return RayParams(delta, t_max, sigma0, eta_minus, eta_plus, safety, int(max_iters), 1 if clip_to_domain else 0)
+
+
+def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
+    import torch
+    n = origin.shape[0]
+    rp = ray_params(**params)
+    st = lib().spk_cast_rays(ctx.handle, net.handle, ctypes.byref(rp), n,
+                             _ptr(origin, torch.float32, (n, 3), "origin"),
+                             _ptr(direction, torch.float32, (n, 3), "direction"),
+                             _ptr(t_hit, torch.float32, (n,), "t_hit"), _ptr(iters, torch.int32, (n,), "iters"))
+    _check(st, "spk_cast_rays")
+
+
+def eval_points(ctx, net, x, f):
+    import torch
+    n = x.shape[0]
+    st = lib().spk_eval_points(ctx.handle, net.handle, n, _ptr(x, torch.float32, (n, 3), "x"),
+                               _ptr(f, torch.float32, (n,), "f"))
+    _check(st, "spk_eval_points")
+
+
+def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3,
+                 cap=1 << 26):
+    """Fixed-depth octree by repeated spk_subdivide_frontier rounds (the
+    breadth-first parallel rounds of Procedure 3).  Returns per-level stats and
+    the UNKNOWN leaf cells at max_level (GPU tensor)."""
+    import torch
+    dev = torch.device("cuda")
+    cells = torch.zeros(1, dtype=torch.int64, device=dev)
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    levels = []
+    leaves = torch.zeros(0, dtype=torch.int64, device=dev)
+    for level in range(max_level + 1):
+        n = cells.shape[0]
+        at_max = level == max_level
+        capc = 0 if at_max else min(8 * n, cap)
+        capl = n if at_max else 0
+        children = torch.empty(max(capc, 1), dtype=torch.int64, device=dev)
+        lv = torch.empty(max(capl, 1), dtype=torch.int64, device=dev)
+        subdivide_frontier(ctx, net, level, cells, children[:capc] if capc else None, lv[:capl] if capl else None,
+                           counts, max_level, policy, k, dom_lo, dom_hi)
+        c = counts.cpu().tolist()
+        levels.append({"level": level, "n": n, "n_children": c[0], "n_leaves": c[1], "n_pos": c[2], "n_neg": c[3]})
+        if at_max:
+            leaves = lv[:c[1]]
+            break
+        if c[0] > capc:
+            raise SpkError(E_NOSPC, "build_octree")
+        cells = children[:c[0]]
+    return levels, leaves

@@ -1,0 +1,93 @@
+"""Parity helpers shared by the GPU tests: run the HIP path through the C ABI
+and compare with the FP64 oracle (the HIP side never feeds the oracle except
+for the explicit truncation replay, which only re-plays its kept sets)."""
+import numpy as np
+
+from oracle import mlp as omlp
+from oracle import queries as oq
+
+TOL = 1e-5   # relative parity tolerance of the bound endpoints
+
+
+def s_net(net, n=4096, seed=1234):
+    """RMS of f over seeded uniform points of [-1,1]^3: the scale of f."""
+    rng = np.random.default_rng(seed)
+    f = omlp.forward(net, rng.uniform(-1, 1, (n, 3)))
+    return float(np.sqrt(np.mean(f * f)))
+
+
+def gpu_classify(ctx, g, lo, hi, policy, k, want_src=False):
+    import torch
+    from paper_2202_02444_amd import spk
+    dev = torch.device("cuda")
+    n = lo.shape[0]
+    tl = torch.from_numpy(np.ascontiguousarray(lo)).to(dev)
+    th = torch.from_numpy(np.ascontiguousarray(hi)).to(dev)
+    lab = torch.empty(n, dtype=torch.uint8, device=dev)
+    glo = torch.empty(n, dtype=torch.float32, device=dev)
+    ghi = torch.empty(n, dtype=torch.float32, device=dev)
+    cen = torch.empty(n, dtype=torch.float32, device=dev)
+    rad = torch.empty(n, dtype=torch.float32, device=dev)
+    err = torch.empty(n, dtype=torch.float32, device=dev)
+    aux = {"center": cen, "radius": rad, "err": err}
+    src = None
+    if want_src:
+        src = torch.full((g.n_linear - 1, n, 32), -3, dtype=torch.int16, device=dev)
+        aux["slot_src"] = src
+    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, policy, k, aux=aux)
+    ctx.sync()
+    out = {"label": lab.cpu().numpy(), "lo": glo.cpu().numpy().astype(np.float64),
+           "hi": ghi.cpu().numpy().astype(np.float64), "center": cen.cpu().numpy().astype(np.float64),
+           "radius": rad.cpu().numpy().astype(np.float64), "err": err.cpu().numpy().astype(np.float64)}
+    if want_src:
+        out["src"] = src.cpu().numpy()
+    return out
+
+
+def keep_sets_from_src(src, s, k, H):
+    """Oracle keep masks [B, n_occ + H] per activation from the GPU's slot
+    record (slot C holds oracle column C-1)."""
+    sets = []
+    n_occ = s
+    for a in range(src.shape[0]):
+        rec = src[a]
+        B = rec.shape[0]
+        keep = np.zeros((B, n_occ + H), dtype=bool)
+        keep[:, :n_occ] = rec[:, 1:n_occ + 1] == -1
+        for C in range(1, 32):
+            r = rec[:, C]
+            m = r >= 0
+            keep[np.flatnonzero(m), n_occ + r[m]] = True
+        sets.append(keep)
+        n_occ = min(k, n_occ + H)
+    return sets
+
+
+def endpoint_errors(c_g, r_g, lo_o, hi_o, S):
+    return np.maximum(np.abs((c_g - r_g) - lo_o), np.abs((c_g + r_g) - hi_o)) / S
+
+
+def label_ambiguous(lo_o, hi_o, S, err_g):
+    tau = TOL * S + err_g * 1.01
+    return (np.abs(lo_o) <= tau) | (np.abs(hi_o) <= tau)
+
+
+def sample_points(lo, hi, rng, n_rand=8):
+    """Box corners, center and random points for each box: [B, 9 + n_rand, 3]."""
+    lo = lo.astype(np.float64)
+    hi = hi.astype(np.float64)
+    corners = np.array(np.meshgrid([0, 1], [0, 1], [0, 1], indexing="ij")).reshape(3, -1).T.astype(np.float64)
+    t = np.concatenate([corners, [[0.5, 0.5, 0.5]], rng.uniform(0, 1, (n_rand, 3))])
+    return lo[:, None, :] + t[None] * (hi - lo)[:, None, :]
+
+
+def soundness_violations(net, lo, hi, glo, ghi, rng, n_rand=8):
+    P = sample_points(lo, hi, rng, n_rand)
+    B, m, _ = P.shape
+    f = omlp.forward(net, P.reshape(-1, 3)).reshape(B, m)
+    bad = (f < glo[:, None]) | (f > ghi[:, None])
+    return int(bad.sum()), f
+
+
+def oracle_labels(lo_o, hi_o):
+    return oq.classify(lo_o, hi_o)

@@ -1,0 +1,105 @@
+"""The C ABI library loads, exports every symbol include/spk.h declares, and
+rejects invalid arguments before touching the GPU (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_02444_amd import spk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "spk.h")).read()
+    return sorted(set(re.findall(r"\b(spk_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = spk.lib()
+    names = _declared()
+    assert "spk_classify_boxes" in names and "spk_cast_rays" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(spk.EXPORTS) <= set(names)
+
+
+def test_status_strings_and_version():
+    L = spk.lib()
+    for s in range(7):
+        assert L.spk_status_str(s)
+    assert b"gfx950" in L.spk_version()
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced on the validation paths below
+
+
+def test_net_create_rejects_bad_shapes():
+    L = spk.lib()
+    out = ctypes.c_void_p()
+    W = [np.zeros((48, 3), np.float32), np.zeros((1, 48), np.float32)]
+    b = [np.zeros(48, np.float32), np.zeros(1, np.float32)]
+    wa = (ctypes.c_int32 * 3)(3, 48, 1)
+    Wp = (ctypes.c_void_p * 2)(*[w.ctypes.data for w in W])
+    bp = (ctypes.c_void_p * 2)(*[x.ctypes.data for x in b])
+    assert L.spk_net_create(2, wa, Wp, bp, 0, 1.0, ctypes.byref(out)) == spk.E_UNSUPPORTED   # width 48
+    wa2 = (ctypes.c_int32 * 3)(2, 32, 1)
+    assert L.spk_net_create(2, wa2, Wp, bp, 0, 1.0, ctypes.byref(out)) == spk.E_UNSUPPORTED  # input dim 2
+    wa3 = (ctypes.c_int32 * 3)(3, 32, 1)
+    assert L.spk_net_create(2, wa3, Wp, bp, 7, 1.0, ctypes.byref(out)) == spk.E_INVAL        # activation
+    assert L.spk_net_create(2, wa3, Wp, bp, 2, -1.0, ctypes.byref(out)) == spk.E_INVAL       # omega0
+    assert L.spk_net_create(2, wa3, Wp, bp, 0, 1.0, None) == spk.E_INVAL
+    assert L.spk_net_create(1, wa3, Wp, bp, 0, 1.0, ctypes.byref(out)) == spk.E_UNSUPPORTED
+    Wn = [np.full((32, 3), np.nan, np.float32), np.zeros((1, 32), np.float32)]
+    Wnp = (ctypes.c_void_p * 2)(*[w.ctypes.data for w in Wn])
+    bn = [np.zeros(32, np.float32), np.zeros(1, np.float32)]
+    bnp = (ctypes.c_void_p * 2)(*[x.ctypes.data for x in bn])
+    assert L.spk_net_create(2, wa3, Wnp, bnp, 0, 1.0, ctypes.byref(out)) == spk.E_INVAL      # non-finite
+
+
+def test_bound_calls_validate_before_launch():
+    L = spk.lib()
+    o = spk.opts("truncate", 31)
+    assert L.spk_classify_boxes(None, FAKE, ctypes.byref(o), 4, FAKE, FAKE, FAKE, None, None, None) == spk.E_INVAL
+    assert L.spk_classify_boxes(FAKE, FAKE, None, 4, FAKE, FAKE, FAKE, None, None, None) == spk.E_INVAL
+    bad = spk.opts("truncate", 40)
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(bad), 4, FAKE, FAKE, FAKE, None, None,
+                                None) == spk.E_UNSUPPORTED
+    full = spk.opts("full", 0)
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(full), 4, FAKE, FAKE, FAKE, None, None,
+                                None) == spk.E_UNSUPPORTED
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(o), -1, FAKE, FAKE, FAKE, None, None, None) == spk.E_INVAL
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(o), 0, None, None, None, None, None, None) == spk.OK
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(o), 4, None, FAKE, FAKE, None, None, None) == spk.E_INVAL
+    assert L.spk_range_bound(FAKE, FAKE, ctypes.byref(o), 4, 4, FAKE, FAKE, FAKE, FAKE, None) == spk.E_INVAL
+    assert L.spk_range_bound(FAKE, FAKE, ctypes.byref(o), 0, 3, None, None, None, None, None) == spk.OK
+    fx = spk.opts("fixed", 0)
+    aux = spk.BoundAux(None, None, None, FAKE)
+    assert L.spk_range_bound(FAKE, FAKE, ctypes.byref(fx), 4, 3, FAKE, FAKE, FAKE, FAKE,
+                             ctypes.byref(aux)) == spk.E_INVAL
+
+
+def test_tree_and_ray_validation():
+    L = spk.lib()
+    o = spk.opts("truncate", 31)
+    tp = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8)
+    cnt = FAKE
+    assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 7, FAKE, 1, FAKE, 8, None, 0,
+                                    cnt) == spk.E_INVAL      # level beyond max_level
+    tp2 = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 2)
+    assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp2), 0, FAKE, 1, FAKE, 8, None, 0,
+                                    cnt) == spk.E_UNSUPPORTED
+    tp3 = spk.TreeParams((ctypes.c_float * 3)(1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8)
+    assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp3), 0, FAKE, 1, FAKE, 8, None, 0,
+                                    cnt) == spk.E_INVAL      # empty domain
+    assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 0, FAKE, 1, None, 8, None, 0,
+                                    cnt) == spk.E_INVAL      # capacity without buffer
+    rp = spk.ray_params()
+    assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp), -1, FAKE, FAKE, FAKE, None) == spk.E_INVAL
+    assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp), 0, None, None, None, None) == spk.OK
+    rp_bad = spk.ray_params(delta=-1.0)
+    assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp_bad), 4, FAKE, FAKE, FAKE, None) == spk.E_INVAL
+    rp_bad2 = spk.ray_params(eta_minus=1.5)
+    assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp_bad2), 4, FAKE, FAKE, FAKE, None) == spk.E_INVAL
