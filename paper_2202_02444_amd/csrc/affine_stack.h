@@ -1,0 +1,513 @@
+// The affine-arithmetic network pass shared by the bound and ray kernels.
+//
+// A wavefront owns BPW boxes (or ray segments).  The steps:
+//   activate()      activation linearisation + condensation, owner layout
+//                   (eq. affine_func_update, Table 3, Section 3.3)
+//   hidden_layer()  one H -> H layer: generators Y = W X on FP32 MFMA, the
+//                   center W x0 in FP64, |W| xinf and the rounding-error
+//                   product |W| u on VALU alongside (Table 2 matrix
+//                   multiplication)
+//   output_layer()  the H -> 1 layer and the range read-off (eq. def_range)
+//
+// "Passenger" slots (the last NPASS term slots) carry plain point
+// evaluations through the same GEMMs: they receive the bias and the exact
+// activation instead of the linearisation, and are excluded from the radius.
+// The ray-march kernel uses them for the convergence test of Procedure 2.
+#pragma once
+
+#include "affine_core.h"
+
+namespace spk {
+
+constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
+
+template <class S>
+struct LdsState {
+  float tile[S::TILE];
+  float vinf[256];
+  float vu[256];
+  double vc[256];
+};
+
+template <int ACT>
+__device__ __forceinline__ float act_point(float x, float omega0) {
+  if (ACT == SPK_ACT_RELU) return fmaxf(x, 0.0f);
+  if (ACT == SPK_ACT_ELU) return x > 0.0f ? x : expm1f(x);
+  return sinf(omega0 * x);
+}
+
+template <int SEG>
+__device__ __forceinline__ double seg_allsum_d(double v) {
+#pragma unroll
+  for (int m = 1; m < SEG; m <<= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Round a double to a float that is <= / >= it.
+__device__ __forceinline__ float round_down_f(double v) {
+  float f = (float)v;
+  return ((double)f > v) ? next_down(f) : f;
+}
+__device__ __forceinline__ float round_up_f(double v) {
+  float f = (float)v;
+  return ((double)f < v) ? next_up(f) : f;
+}
+
+// Activation + condensation on the owner-layout rows.  On entry xc holds the
+// pre-activation centers (FP64, bias included), y the generator terms in
+// slots 1.. (slot 0 is unused), yinf the condensed term and e the error
+// radius.  On exit xc/y/yinf/e hold the post-activation form and u = e + cK r
+// + cD |x0| is the vector the next layer's rounding-error product |W| u needs.
+// Returns the new number of occupied generator slots.
+template <class S, int ACT, int POL, int NPASS>
+__device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], float (&yinf)[4], float (&e)[4],
+                                        float (&u)[4], int n_occ, int k, float cK, float cD, float omega0, int lane,
+                                        int16_t* rec) {
+  static_assert(NPASS == 0 || POL == SPK_AFFINE_FIXED, "passengers ride along affine-fixed passes only");
+  constexpr int NG = S::NS - NPASS;   // slots 1..NG-1 are generators
+  float gam[4], rnext[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int C = NG; C < S::NS; ++C) y[i][C] = act_point<ACT>(y[i][C], omega0);
+    if (ACT == SPK_ACT_SIN) {
+      // Table 2 constant multiplication by omega0 before sin
+      float rs = 0.0f;
+#pragma unroll
+      for (int C = 1; C < NG; ++C) {
+        y[i][C] *= omega0;
+        rs += fabsf(y[i][C]);
+      }
+      yinf[i] *= omega0;
+      xc[i] *= (double)omega0;
+      e[i] = (e[i] * omega0 + kU * (rs + yinf[i])) * kGrow + (float)(2.0 * kU64) * (float)fabs(xc[i]) + kEta;
+    }
+    const double x0 = xc[i];
+    float rY = 0.0f;
+#pragma unroll
+    for (int C = 1; C < NG; ++C) rY += fabsf(y[i][C]);
+    const float r = rY + yinf[i];
+    const double xl = x0 - (double)r, xu = x0 + (double)r;
+    const ActOut p = act_params<ACT>(xl, xu, x0);
+    const float alf = (float)p.al;
+    // rounding of the range read-off (the FP32 sum r)
+    const float rho = (float)(S::NS + 3) * kU * r + kEta;
+    const float ext = e[i] + rho;
+    bool exact;
+    if (ACT == SPK_ACT_RELU)
+      exact = (p.al == 1.0 && xl - (double)ext >= 0.0) || (p.al == 0.0 && xu + (double)ext <= 0.0);
+    else if (ACT == SPK_ACT_ELU)
+      exact = p.al == 1.0 && xl - (double)ext >= 0.0;
+    else
+      exact = false;
+    // the linearisation holds on [xl, xu] up to gamma; on the rounding
+    // neighbourhood it degrades by at most lip * ext (unless it is exact there)
+    float ep = fabsf(alf) * e[i] + (exact ? 0.0f : p.lip * ext + p.dg);
+    const double z0 = fma(p.al, x0, p.be);
+#pragma unroll
+    for (int C = 1; C < NG; ++C) y[i][C] *= alf;
+    xc[i] = z0;
+    y[i][0] = (float)z0;
+    const float zi = fabsf(alf) * yinf[i];
+    // FP32 slope applied to the generators (2u: slope rounding + product),
+    // condensed-term product, FP64 center update
+    ep += 2.0f * kU * (fabsf(alf) * rY + zi) + (float)(2.0 * kU64) * (float)fabs(z0);
+    yinf[i] = zi;
+    // gamma rounded to FP32; the rounding goes into the error radius
+    gam[i] = fmaxf((float)p.ga, 0.0f);
+    e[i] = ep + kU * gam[i];
+    rnext[i] = fabsf(alf) * r + gam[i];
+  }
+
+  int n_occ_new = n_occ;
+  if (POL == SPK_AFFINE_FIXED) {
+    // affine-fixed: every new term goes straight into the condensed coefficient
+#pragma unroll
+    for (int i = 0; i < 4; ++i) yinf[i] += gam[i];
+  } else {
+    // affine-truncate(k): candidates are the occupied old slots 1..n_occ
+    // (magnitude = column L1 norm over the box's H rows) and the H new terms
+    // (magnitude gamma_j); keep the k largest, ties to the lower candidate
+    // index (old slots in slot order, then new terms by neuron index).
+    constexpr int SEG = S::SEG;
+    const int ch = lane % SEG;
+    uint32_t kold[S::NS];
+    kold[0] = 0u;
+#pragma unroll
+    for (int C = 1; C < S::NS; ++C) {
+      const float mu = seg_allsum<SEG>((fabsf(y[0][C]) + fabsf(y[1][C])) + (fabsf(y[2][C]) + fabsf(y[3][C])));
+      kold[C] = __float_as_uint(mu) & 0x7fffffffu;
+    }
+    uint32_t knew[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) knew[i] = __float_as_uint(gam[i]) & 0x7fffffffu;
+    // old candidates this lane counts: slots C with (C-1) % SEG == ch
+    constexpr int Q = (S::NS - 1 + SEG - 1) / SEG;
+    uint32_t mine[Q];
+    bool minev[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) { mine[q] = 0u; minev[q] = false; }
+#pragma unroll
+    for (int C = 1; C < S::NS; ++C) {
+      const int q = (C - 1) / SEG;
+      const bool sel = ((C - 1) % SEG) == ch;
+      mine[q] = sel ? kold[C] : mine[q];
+      minev[q] = sel ? (C <= n_occ) : minev[q];
+    }
+    // radix select of the k-th largest key, most significant bit first
+    uint32_t T = 0u;
+#pragma unroll 1
+    for (int bit = 30; bit >= 0; --bit) {
+      const uint32_t Tc = T | (1u << bit);
+      int cnt = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cnt += seg_count<SEG>(minev[q] && mine[q] >= Tc, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cnt += seg_count<SEG>(knew[i] >= Tc, lane);
+      T = (cnt >= k) ? Tc : T;
+    }
+    const uint32_t tau = T;
+    int cgt = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) cgt += seg_count<SEG>(minev[q] && mine[q] > tau, lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cgt += seg_count<SEG>(knew[i] > tau, lane);
+    const int need = k - cgt;
+    // old slots: equal-to-tau ones ranked by slot
+    uint32_t eqm = 0u, keep_old = 0u;
+#pragma unroll
+    for (int C = 1; C < S::NS; ++C) {
+      const bool v = C <= n_occ;
+      eqm |= (v && kold[C] == tau) ? (1u << C) : 0u;
+    }
+#pragma unroll
+    for (int C = 1; C < S::NS; ++C) {
+      const bool v = C <= n_occ;
+      const bool kp = v && (kold[C] > tau || (kold[C] == tau && __popc(eqm & ((1u << C) - 1u)) < need));
+      keep_old |= kp ? (1u << C) : 0u;
+    }
+    const int n_eq_old = __popc(eqm);
+    // new terms: rank among equal keys by neuron (row) index
+    int run = n_eq_old;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) run += seg_count_below<SEG>(knew[i] == tau, lane);
+    bool keepnew[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool eq = knew[i] == tau;
+      keepnew[i] = knew[i] > tau || (eq && run < need);
+      run += eq ? 1 : 0;
+    }
+    // free slots (dropped old, then empty ones up to k) receive the kept new
+    // terms in increasing slot order by increasing neuron index
+    const uint32_t occm = (n_occ >= 31) ? 0xfffffffeu : ((1u << (n_occ + 1)) - 2u);
+    const uint32_t kmsk = (k >= 31) ? 0xfffffffeu : ((1u << (k + 1)) - 2u);
+    uint32_t freem = (occm & ~keep_old) | (kmsk & ~occm);
+    if (S::BPW == 1) freem = __builtin_amdgcn_readfirstlane(freem);
+    int rk = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rk += seg_count_below<SEG>(keepnew[i], lane);
+    int slot[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      slot[i] = keepnew[i] ? nth_set_bit(freem, rk) : -1;
+      rk += keepnew[i] ? 1 : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float zi = yinf[i];
+#pragma unroll
+      for (int C = 1; C < S::NS; ++C) {
+        if ((freem >> C) & 1u) {
+          zi += fabsf(y[i][C]);
+          y[i][C] = (slot[i] == C) ? gam[i] : 0.0f;
+        }
+      }
+      zi += keepnew[i] ? 0.0f : gam[i];
+      yinf[i] = zi;
+    }
+    if (rec != nullptr) {
+      if (ch == 0) {
+        for (int C = 0; C < 32; ++C) {
+          const bool fr = (freem >> C) & 1u;
+          if (!fr) rec[C] = (C == 0 || C <= k) ? (int16_t)-1 : (int16_t)-2;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (slot[i] >= 0) rec[slot[i]] = (int16_t)(4 * ch + i);
+    }
+    n_occ_new = (n_occ + S::H < k) ? n_occ + S::H : k;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float ef = e[i] * kGrow + (float)(S::NS + 2) * kU * yinf[i] + kEta;
+    e[i] = ef;
+    u[i] = ef + (cK * rnext[i] + cD * (float)fabs(xc[i])) * kGrowR;
+  }
+  return n_occ_new;
+}
+
+// One hidden layer (index a among the H -> H layers) from owner layout to
+// owner layout through the LDS tile.  Ends with the pre-activation form of
+// the next activation: centers with bias (FP64), generators, condensed term,
+// error radius; passengers receive the bias too.
+template <class S, int NPASS>
+__device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm, int a, double (&xc)[4],
+                                             float (&y)[4][S::NS], float (&yinf)[4], float (&e)[4],
+                                             const float (&u)[4], int lane) {
+  constexpr int H = S::H, MT = S::MT, NT = S::NT, NS = S::NS, BPW = S::BPW, SEG = S::SEG;
+  const int g = lane >> 4, c = lane & 15;
+  const int bo = lane / SEG;
+  const int ch = lane % SEG;
+  const float cK = net.cK;
+
+  // ---- owner layout -> LDS ----
+#pragma unroll
+  for (int C = 0; C < NS; ++C) {
+    f4 v = {y[0][C], y[1][C], y[2][C], y[3][C]};
+    *(f4*)&sm.tile[taddr<S>(bo, C, ch)] = v;
+  }
+  {
+    f4 v1 = {yinf[0], yinf[1], yinf[2], yinf[3]};
+    f4 v2 = {u[0], u[1], u[2], u[3]};
+    *(f4*)&sm.vinf[4 * lane] = v1;
+    *(f4*)&sm.vu[4 * lane] = v2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sm.vc[4 * lane + i] = xc[i];
+  }
+  __syncthreads();
+
+  // ---- generators on MFMA, center in FP64, |W| xinf and |W| u on VALU ----
+  f4 acc[MT][BPW * NT];
+  float px[MT][BPW], pe[MT][BPW];
+  double pd[MT][BPW];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+#pragma unroll
+    for (int q = 0; q < BPW * NT; ++q) acc[tp][q] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) { px[tp][b] = 0.0f; pe[tp][b] = 0.0f; pd[tp][b] = 0.0; }
+  }
+  const f4* Wl = (const f4*)net.Wp + (size_t)a * (H * H / 4);
+  if constexpr (BPW == 1) {
+    // one box: stream the A fragments, each used by NT MFMAs right away
+#pragma unroll 1
+    for (int t = 0; t < MT; ++t) {
+      f4 bfr[NT];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) bfr[n] = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * t + g)];
+      const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
+      const f4 ve = *(const f4*)&sm.vu[16 * t + 4 * g];
+      double vd[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
+      const f4* Wt = Wl + (size_t)t * MT * 64 + lane;
+#pragma unroll
+      for (int tp = 0; tp < MT; ++tp) {
+        const f4 w = Wt[tp * 64];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[tp][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], bfr[n][j], acc[tp][n], 0, 0, 0);
+          px[tp][0] = fmaf(fabsf(w[j]), vx[j], px[tp][0]);
+          pe[tp][0] = fmaf(fabsf(w[j]), ve[j], pe[tp][0]);
+          pd[tp][0] = fma((double)w[j], vd[j], pd[tp][0]);
+        }
+      }
+    }
+  } else {
+    // several boxes: hold this K block's A fragments for every output tile
+    // (MT is small here) and reuse them box after box, so only one box's B
+    // operands are live at a time
+#pragma unroll 1
+    for (int t = 0; t < MT; ++t) {
+      f4 w[MT];
+      const f4* Wt = Wl + (size_t)t * MT * 64 + lane;
+#pragma unroll
+      for (int tp = 0; tp < MT; ++tp) w[tp] = Wt[tp * 64];
+#pragma unroll
+      for (int b = 0; b < BPW; ++b) {
+        f4 bfr[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) bfr[n] = *(const f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * t + g)];
+        const f4 vx = *(const f4*)&sm.vinf[b * H + 16 * t + 4 * g];
+        const f4 ve = *(const f4*)&sm.vu[b * H + 16 * t + 4 * g];
+        double vd[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vd[j] = sm.vc[b * H + 16 * t + 4 * g + j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int tp = 0; tp < MT; ++tp) {
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+              acc[tp][b * NT + n] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(w[tp][j], bfr[n][j], acc[tp][b * NT + n], 0, 0, 0);
+            px[tp][b] = fmaf(fabsf(w[tp][j]), vx[j], px[tp][b]);
+            pe[tp][b] = fmaf(fabsf(w[tp][j]), ve[j], pe[tp][b]);
+            pd[tp][b] = fma((double)w[tp][j], vd[j], pd[tp][b]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- MFMA layout -> LDS -> owner layout ----
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      float sx = px[tp][b], se = pe[tp][b];
+      double sd = pd[tp][b];
+      sx += __shfl_xor(sx, 16, 64);
+      se += __shfl_xor(se, 16, 64);
+      sd += __shfl_xor(sd, 16, 64);
+      sx += __shfl_xor(sx, 32, 64);
+      se += __shfl_xor(se, 32, 64);
+      sd += __shfl_xor(sd, 32, 64);
+      if (g == 0) {
+        sm.vinf[b * H + 16 * tp + c] = sx;
+        sm.vu[b * H + 16 * tp + c] = se;
+        sm.vc[b * H + 16 * tp + c] = sd;
+      }
+#pragma unroll
+      for (int n = 0; n < NT; ++n) *(f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * tp + g)] = acc[tp][b * NT + n];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int C = 1; C < NS; ++C) {
+    const f4 v = *(const f4*)&sm.tile[taddr<S>(bo, C, ch)];
+    y[0][C] = v.x; y[1][C] = v.y; y[2][C] = v.z; y[3][C] = v.w;
+  }
+  {
+    const f4 xi = *(const f4*)&sm.vinf[4 * lane];
+    const f4 eu = *(const f4*)&sm.vu[4 * lane];
+    const f4 bh = *(const f4*)&net.bh[(size_t)a * H + 4 * ch];
+    const f4 eb = *(const f4*)&net.ebh[(size_t)a * H + 4 * ch];
+    const float grow = 1.0f + 2.0f * cK;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xc[i] = sm.vc[4 * lane + i] + (double)bh[i];
+      y[i][0] = (float)xc[i];
+#pragma unroll
+      for (int C = NS - NPASS; C < NS; ++C) y[i][C] += bh[i];
+      yinf[i] = xi[i];
+      e[i] = eu[i] * grow + eb[i];
+    }
+  }
+  __syncthreads();
+}
+
+struct OutVals {
+  double y0;    // center
+  float r;      // raw radius
+  float err;    // rounding-error radius
+};
+
+// Output layer (H -> 1) and range read-off, reduced over the box's segment
+// (every lane of the segment gets the same values).  pass[] receives the
+// passengers' plain evaluations f(x).
+template <class S, int NPASS>
+__device__ __forceinline__ OutVals output_layer(const NetDev& net, const double (&xc)[4], const float (&y)[4][S::NS],
+                                                const float (&yinf)[4], const float (&u)[4], int lane,
+                                                float (&pass)[NPASS > 0 ? NPASS : 1]) {
+  constexpr int NS = S::NS, SEG = S::SEG, NG = NS - NPASS;
+  const int ch = lane % SEG;
+  const float cK = net.cK;
+  const f4 wv = *(const f4*)&net.wL[4 * ch];
+  double p0 = 0.0;
+  float pinf = 0.0f, pu = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    p0 = fma((double)wv[i], xc[i], p0);
+    pinf = fmaf(fabsf(wv[i]), yinf[i], pinf);
+    pu = fmaf(fabsf(wv[i]), u[i], pu);
+  }
+  p0 = seg_allsum_d<SEG>(p0);
+  pinf = seg_allsum<SEG>(pinf);
+  pu = seg_allsum<SEG>(pu);
+  float r = 0.0f;
+#pragma unroll
+  for (int C = 1; C < NG; ++C) {
+    float pc = wv[0] * y[0][C];
+    pc = fmaf(wv[1], y[1][C], pc);
+    pc = fmaf(wv[2], y[2][C], pc);
+    pc = fmaf(wv[3], y[3][C], pc);
+    r += fabsf(seg_allsum<SEG>(pc));
+  }
+#pragma unroll
+  for (int C = NG; C < NS; ++C) {
+    float pc = wv[0] * y[0][C];
+    pc = fmaf(wv[1], y[1][C], pc);
+    pc = fmaf(wv[2], y[2][C], pc);
+    pc = fmaf(wv[3], y[3][C], pc);
+    pass[C - NG] = seg_allsum<SEG>(pc) + net.bL;
+  }
+  r += pinf;
+  OutVals o;
+  o.y0 = p0 + (double)net.bL;
+  o.r = r;
+  o.err = (pu * (1.0f + 2.0f * cK) + net.eL + (float)(NS + 3) * kU * r + (float)(4.0 * kU64) * (float)fabs(o.y0)) *
+              kGrow + kEta;
+  return o;
+}
+
+// Sound FP32 enclosure [lo, hi] of center +- (radius + err); non-finite
+// results become [-inf, +inf].
+__device__ __forceinline__ void enclose(const OutVals& o, float& lo, float& hi) {
+  const double s = ((double)o.r + (double)o.err) * (1.0 + 4.0 * kU64);
+  lo = round_down_f(o.y0 - s);
+  hi = round_up_f(o.y0 + s);
+  if (!(lo <= hi) || !(lo > -INFINITY) || !(hi < INFINITY)) {
+    lo = -INFINITY;
+    hi = INFINITY;
+  }
+}
+
+// Layer 0 applied to an affine input with FP64 center cc, FP32 axes ax[q]
+// (q < 3; unused axes zero) and per-coordinate input error radius ein, plus
+// NPASS passenger points.  Owner layout: rows 4ch..4ch+3.
+template <class S, int NPASS>
+__device__ __forceinline__ void layer0_affine(const NetDev& net, int ch, const double (&cc)[3],
+                                              const float (&ax)[3][3], const float (&ein)[3],
+                                              const float (&pts)[NPASS > 0 ? NPASS : 1][3], double (&xc)[4],
+                                              float (&y)[4][S::NS], float (&yinf)[4], float (&e)[4]) {
+  constexpr int NG = S::NS - NPASS;
+  const f4* W0 = (const f4*)net.W0;   // rows padded to 4 floats
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = 4 * ch + i;
+    const f4 w = W0[R];
+    const float bb = net.b0[R];
+    xc[i] = fma((double)w.z, cc[2], fma((double)w.y, cc[1], fma((double)w.x, cc[0], (double)bb)));
+    const float cmag = (float)(fabs((double)w.x * cc[0]) + fabs((double)w.y * cc[1]) + fabs((double)w.z * cc[2])) +
+                       fabsf(bb);
+    y[i][0] = (float)xc[i];
+    // generator columns 1..3 = W0 times the box axes; the rest start empty
+    const float g0 = fmaf(w.z, ax[0][2], fmaf(w.y, ax[0][1], w.x * ax[0][0]));
+    const float g1 = fmaf(w.z, ax[1][2], fmaf(w.y, ax[1][1], w.x * ax[1][0]));
+    const float g2 = fmaf(w.z, ax[2][2], fmaf(w.y, ax[2][1], w.x * ax[2][0]));
+    const float gmag = fabsf(w.x) * (fabsf(ax[0][0]) + fabsf(ax[1][0]) + fabsf(ax[2][0])) +
+                       fabsf(w.y) * (fabsf(ax[0][1]) + fabsf(ax[1][1]) + fabsf(ax[2][1])) +
+                       fabsf(w.z) * (fabsf(ax[0][2]) + fabsf(ax[1][2]) + fabsf(ax[2][2]));
+    y[i][1] = g0;
+    y[i][2] = g1;
+    y[i][3] = g2;
+#pragma unroll
+    for (int C = 4; C < NG; ++C) y[i][C] = 0.0f;
+#pragma unroll
+    for (int C = NG; C < S::NS; ++C) {
+      const int q = C - NG;
+      y[i][C] = fmaf(w.z, pts[q][2], fmaf(w.y, pts[q][1], fmaf(w.x, pts[q][0], bb)));
+    }
+    yinf[i] = 0.0f;
+    e[i] = (net.c3 * gmag + (float)(8.0 * kU64) * cmag + fabsf(w.x) * ein[0] + fabsf(w.y) * ein[1] +
+            fabsf(w.z) * ein[2]) * kGrow + kEta;
+  }
+}
+
+}  // namespace spk

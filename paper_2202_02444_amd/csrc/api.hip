@@ -334,7 +334,10 @@ spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params*
   if (!p.clip_to_domain && !(p.t_max > 0.0f && isfinite(p.t_max))) return SPK_E_INVAL;
   if (n == 0) return SPK_OK;
   if (origin == nullptr || dir == nullptr || t_hit == nullptr) return SPK_E_INVAL;
-  return launch_rays(net, p, n, origin, dir, t_hit, iters, ctx->stream, ctx->num_cus);
+  void* counter = nullptr;
+  spk_status st = ctx_scratch(ctx, 256, &counter);
+  if (st != SPK_OK) return st;
+  return launch_rays(net, p, n, origin, dir, t_hit, iters, (unsigned long long*)counter, ctx->stream, ctx->num_cus);
 }
 
 spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f) {

@@ -88,5 +88,6 @@ spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t 
 spk_status launch_eval(const spk_net* net, int64_t n, const float* x, float* f, hipStream_t stream,
                        int num_cus);
 spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, const float* origin,
-                       const float* dir, float* t_hit, int32_t* iters, hipStream_t stream, int num_cus);
+                       const float* dir, float* t_hit, int32_t* iters, unsigned long long* counter,
+                       hipStream_t stream, int num_cus);
 }  // namespace spk

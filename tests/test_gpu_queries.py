@@ -1,0 +1,202 @@
+"""GPU parity of the octree rounds (Procedure 3) and ray casting (Procedure 2)
+against the FP64 oracle and closed forms, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as omlp
+from oracle import queries as oq
+
+from parity import TOL, label_ambiguous, s_net
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2202_02444_amd import spk
+    c = spk.Context()
+    yield c
+    c.close()
+
+
+def _gpu_tree(ctx, net, depth, policy, k):
+    from paper_2202_02444_amd import spk
+    g = spk.Net.from_spec(net)
+    levels, leaves = spk.build_octree(ctx, g, depth, policy, k)
+    return levels, np.sort(leaves.cpu().numpy().astype(np.uint64))
+
+
+@pytest.mark.parametrize("policy,k", [("truncate", 16), ("fixed", 0)])
+def test_octree_depth6_tiny(ctx, policy, k):
+    """Config-1 octree: every GPU cell's label equals the oracle's label of that
+    cell unless the oracle bound is within the parity band of zero; the tree
+    partitions the domain exactly; leaf sets agree up to ambiguous subtrees."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.tiny_net(0)
+    depth = 6
+    g = spk.Net.from_spec(net)
+    dev = torch.device("cuda")
+    cells = torch.zeros(1, dtype=torch.int64, device=dev)
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    Snet = s_net(net)
+    vol = 0.0
+    n_amb = 0
+    for level in range(depth + 1):
+        n = cells.shape[0]
+        at_max = level == depth
+        children = torch.empty(max(8 * n, 1), dtype=torch.int64, device=dev)
+        leaves = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        spk.subdivide_frontier(ctx, g, level, cells, None if at_max else children[:8 * n],
+                               leaves[:n] if at_max else None, counts, depth, policy, k)
+        c = counts.cpu().numpy()
+        codes = cells.cpu().numpy().astype(np.uint64)
+        lo, hi = oq.cell_bounds(codes, level, (-1,) * 3, (1,) * 3)
+        _, _, lo_o, hi_o = omlp.bound_boxes(net, lo, hi, policy, max(k, 3))
+        lab_o = oq.classify(lo_o, hi_o)
+        S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), Snet)
+        amb = label_ambiguous(lo_o, hi_o, S, TOL * S)
+        n_amb += int(amb.sum())
+        # GPU counts vs oracle labels of the same cells
+        unk_o = int((lab_o == oq.UNKNOWN).sum())
+        n_unk_g = c[1] if at_max else c[0] // 8
+        assert abs(n_unk_g - unk_o) <= amb.sum()
+        assert abs(c[2] - int((lab_o == oq.POSITIVE).sum())) <= amb.sum()
+        assert abs(c[3] - int((lab_o == oq.NEGATIVE).sum())) <= amb.sum()
+        vol += (c[2] + c[3]) * 8.0 / 8 ** level
+        if at_max:
+            vol += c[1] * 8.0 / 8 ** level
+            got = np.sort(leaves[:c[1]].cpu().numpy().astype(np.uint64))
+            want = np.sort(codes[lab_o == oq.UNKNOWN])
+            assert len(np.setxor1d(got, want)) <= amb.sum()
+            break
+        kids = children[:c[0]].cpu().numpy().astype(np.uint64)
+        parents = np.unique(kids >> np.uint64(3))
+        assert np.all(np.isin(parents, codes))
+        assert np.array_equal(np.sort(kids), np.sort(((parents[:, None] << np.uint64(3)) |
+                                                      np.arange(8, dtype=np.uint64)).ravel()))
+        cells = children[:c[0]]
+    assert vol == 8.0
+
+
+def test_octree_matches_oracle_levels(ctx):
+    net = wl.tiny_net(0)
+    levels, leaves = _gpu_tree(ctx, net, 6, "truncate", 31)
+    res = oq.octree_build(net, 6, "truncate", 31)
+    for lg, lo_ in zip(levels, res["levels"]):
+        assert abs(lg["n"] - lo_["n"]) <= max(8, 0.002 * lo_["n"])
+    assert len(np.setxor1d(leaves, res["leaves"])) <= max(8, 0.002 * res["leaves"].size)
+
+
+def test_subdivide_capacity_reports_required(ctx):
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.tiny_net(0)
+    g = spk.Net.from_spec(net)
+    dev = torch.device("cuda")
+    cells = torch.arange(64, dtype=torch.int64, device=dev)   # all level-2 cells
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    small = torch.full((8,), -1, dtype=torch.int64, device=dev)
+    spk.subdivide_frontier(ctx, g, 2, cells, small, None, counts, 6, "truncate", 31)
+    c = counts.cpu().numpy()
+    assert c[0] > 8 and c[0] % 8 == 0          # required count reported
+    assert c[0] // 8 + c[2] + c[3] == 64
+    assert np.all(small.cpu().numpy() >= 0)      # only the capacity was written
+
+
+def _gpu_rays(ctx, net, o, d, **kw):
+    import torch
+    from paper_2202_02444_amd import spk
+    g = spk.Net.from_spec(net)
+    dev = torch.device("cuda")
+    th = torch.empty(o.shape[0], device=dev)
+    it = torch.empty(o.shape[0], dtype=torch.int32, device=dev)
+    spk.cast_rays(ctx, g, torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev), th, it, **kw)
+    ctx.sync()
+    return th.cpu().numpy().astype(np.float64), it.cpu().numpy()
+
+
+def _octahedron_first_hit(p, r, R, T):
+    bps = [0.0] + sorted(t for t in (-p / np.where(r == 0, np.inf, r)) if 0.0 < t < T) + [T]
+    g = lambda t: np.abs(p + t * r).sum() - R
+    for t0, t1 in zip(bps[:-1], bps[1:]):
+        g0, g1 = g(t0), g(t1)
+        if g0 == 0.0:
+            return t0
+        if (g0 > 0) != (g1 > 0):
+            return t0 + g0 * (t1 - t0) / (g0 - g1)
+    return math.inf
+
+
+def test_rays_octahedron_closed_form(ctx):
+    net = wl.octahedron_mlp(0.6, pad_to=32)
+    R = -float(net.biases[1][0])
+    o, d = wl.camera_rays(48, 48, 5, fov_deg=22.0)
+    delta = 1e-3
+    th, it = _gpu_rays(ctx, net, o, d, delta=delta)
+    t_in, t_out, inside = oq.clip_to_box(o, d)
+    n_hit = 0
+    for i in range(o.shape[0]):
+        if not inside[i]:
+            assert math.isinf(th[i])
+            continue
+        p = o[i].astype(np.float64) + t_in[i] * d[i].astype(np.float64)
+        ts = _octahedron_first_hit(p, d[i].astype(np.float64), R, t_out[i] - t_in[i])
+        if math.isinf(ts):
+            assert math.isinf(th[i]), i
+        else:
+            ts += t_in[i]
+            n_hit += 1
+            if math.isinf(th[i]):
+                # the delta contract (Section 4.1) allows missing a feature thinner than delta
+                tt = np.linspace(ts - t_in[i], t_out[i] - t_in[i], 20001)
+                inside_len = (np.abs(p[None, :] + tt[:, None] * d[i].astype(np.float64)).sum(1) < R).mean() * (
+                    t_out[i] - ts)
+                assert inside_len < 2 * delta, (i, inside_len)
+                continue
+            assert ts - delta - 2e-5 <= th[i] <= ts + 2e-5, (i, th[i], ts)
+    assert n_hit > 200
+
+
+@pytest.mark.parametrize("netname", ["tiny", "elu64", "blob"])
+def test_rays_vs_oracle(ctx, netname):
+    if netname == "tiny":
+        net, side = wl.tiny_net(0), 32
+    elif netname == "elu64":
+        net, side = wl.he_normal_mlp([3, 64, 64, 64, 1], 41, act="elu", bias=-0.3), 24
+    else:
+        net, side = wl.scale_net(1), 16
+    o, d = wl.camera_rays(side, side, 7)
+    delta = 1e-3
+    th, it = _gpu_rays(ctx, net, o, d, delta=delta)
+    to, io = oq.cast_rays(net, o.astype(np.float64), d.astype(np.float64), delta=delta)
+    both = np.isfinite(th) & np.isfinite(to)
+    agree = np.isfinite(th) == np.isfinite(to)
+    assert agree.mean() >= 0.98, agree.mean()
+    assert np.all(np.abs(th[both] - to[both]) <= 2 * delta + 1e-4)
+    # every reported hit is a sign change of f within delta
+    hits = np.flatnonzero(np.isfinite(th))
+    for i in hits[:200]:
+        p0 = o[i].astype(np.float64) + th[i] * d[i].astype(np.float64)
+        start = o[i].astype(np.float64) + oq.clip_to_box(o[i:i + 1], d[i:i + 1])[0][0] * d[i].astype(np.float64)
+        f = omlp.forward(net, np.stack([start, p0 + delta * d[i].astype(np.float64)]))
+        assert (f[0] > 0) != (f[1] > 0) or abs(f[1]) < 1e-4 or abs(f[0]) < 1e-4
+
+
+def test_rays_edge_cases(ctx):
+    net = wl.tiny_net(0)
+    o = np.array([[5.0, 5.0, 5.0], [0.0, 0.0, 3.0], [0.0, 0.0, 0.0], [np.nan, 0.0, 0.0]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0], [1.0, 0.0, 0.0]], np.float32)
+    th, it = _gpu_rays(ctx, net, o, d, delta=1e-3)
+    assert math.isinf(th[0]) and it[0] == 0          # misses the cube
+    assert math.isinf(th[3])                          # non-finite origin
+    to, _ = oq.cast_rays(net, o[:3].astype(np.float64), d[:3].astype(np.float64), delta=1e-3)
+    for i in (1, 2):
+        assert np.isfinite(th[i]) == np.isfinite(to[i])
+    th2, it2 = _gpu_rays(ctx, net, o[1:2], d[1:2], delta=1e-3, max_iters=3)
+    assert it2[0] <= 3
