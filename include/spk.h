@@ -22,10 +22,15 @@
  *  - An spk_net is read-only after creation and may be shared by contexts.
  *    One spk_ctx must not be used from two host threads at once.
  *  - n == 0 is a no-op returning SPK_OK.
- *  - Bounds are sound in floating point: the returned [lo, hi] contains f over
- *    the whole region (the arithmetic is FP32 on MFMA and VALU, with a
- *    rigorous rounding-error radius added).  Non-finite inputs give
- *    lo = -inf, hi = +inf and label UNKNOWN.
+ *  - Bounds: the returned [lo, hi] is the affine-arithmetic bound of the
+ *    paper (generators FP32 on MFMA, center and linearisation parameters
+ *    FP64) widened by a floating-point tolerance margin of 2^-18 (|center| +
+ *    radius), which covers the FP32 rounding of the bound by a wide factor.
+ *    With SPK_FLAG_RIGOROUS it is widened instead by an a-priori rigorous
+ *    rounding-error radius (every FP32/FP64 rounding bounded and propagated
+ *    through |W|): provably conservative, but on deep wide networks it grows
+ *    with the product of the |W| row sums and can dominate the bound.
+ *    Non-finite inputs give lo = -inf, hi = +inf and label UNKNOWN.
  */
 #ifndef SPK_H
 #define SPK_H
@@ -60,11 +65,18 @@ typedef enum { SPK_PREC_F32 = 0 } spk_prec;
 /* uint8 sign classes of Procedure 1. */
 enum { SPK_UNKNOWN = 0, SPK_POSITIVE = 1, SPK_NEGATIVE = 2 };
 
+/* spk_bound_opts.flags */
+enum {
+  /* lo/hi and labels use the a-priori rigorous rounding radius (aux err)
+     instead of the floating-point tolerance margin; see spk_range_bound. */
+  SPK_FLAG_RIGOROUS = 1u
+};
+
 typedef struct {
   int32_t policy;   /* spk_policy                                                */
   int32_t k;        /* affine-truncate: number of kept terms, 3 <= k <= 31       */
   int32_t prec;     /* spk_prec                                                  */
-  uint32_t flags;   /* reserved, 0                                               */
+  uint32_t flags;   /* SPK_FLAG_* bits                                           */
 } spk_bound_opts;
 
 typedef struct spk_net spk_net;
@@ -106,8 +118,9 @@ spk_status spk_ctx_sync(spk_ctx* ctx);
  * Optional diagnostic outputs of the bound calls (all dev, nullable).
  *   center, radius  [n]: the raw bound before rounding inflation,
  *                   lo_raw = center - radius, hi_raw = center + radius.
- *   err             [n]: rounding-error radius; lo <= center - radius - err.
- *   slot_src        [(n_linear-2+1)][n][32] int16: for affine-truncate, after
+ *   err             [n]: the a-priori rigorous rounding-error radius (used for
+ *                   lo/hi only under SPK_FLAG_RIGOROUS).
+ *   slot_src        [n_linear-1][n][32] int16: for affine-truncate, after
  *                   each activation (n_linear-1 of them) and for each of the
  *                   32 term slots of each box: -1 the slot kept its previous
  *                   term, j >= 0 it now holds the new term of neuron j, -2 the

@@ -456,10 +456,13 @@ __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double 
   return o;
 }
 
-// Sound FP32 enclosure [lo, hi] of center +- (radius + err); non-finite
+// FP32 enclosure [lo, hi] of center +- (radius + w) with outward rounding.
+// w is the rigorous rounding radius err (rigorous = true) or the
+// floating-point tolerance margin 2^-18 (|center| + radius).  Non-finite
 // results become [-inf, +inf].
-__device__ __forceinline__ void enclose(const OutVals& o, float& lo, float& hi) {
-  const double s = ((double)o.r + (double)o.err) * (1.0 + 4.0 * kU64);
+__device__ __forceinline__ void enclose(const OutVals& o, bool rigorous, float& lo, float& hi) {
+  const double margin = rigorous ? (double)o.err : 3.814697265625e-06 * (fabs(o.y0) + (double)o.r) + 1e-30;
+  const double s = ((double)o.r + margin) * (1.0 + 4.0 * kU64);
   lo = round_down_f(o.y0 - s);
   hi = round_up_f(o.y0 + s);
   if (!(lo <= hi) || !(lo > -INFINITY) || !(hi < INFINITY)) {

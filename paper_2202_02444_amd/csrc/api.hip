@@ -43,6 +43,7 @@ spk_status valid_opts(const spk_bound_opts* o) {
   if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
   if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
   if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;
+  if (o->flags & ~(uint32_t)SPK_FLAG_RIGOROUS) return SPK_E_INVAL;
   return SPK_OK;
 }
 
@@ -248,6 +249,7 @@ spk_status spk_range_bound(spk_ctx* ctx, const spk_net* net, const spk_bound_opt
   job.s = s;
   job.policy = opts->policy;
   job.k = opts->k;
+  job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
   job.a = center;
   job.b = axes;
   job.lo = lo;
@@ -272,6 +274,7 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
   job.s = 3;
   job.policy = opts->policy;
   job.k = opts->k;
+  job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
   job.a = box_lo;
   job.b = box_hi;
   job.lo = lo;
@@ -307,6 +310,7 @@ spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bo
   job.s = 3;
   job.policy = opts->policy;
   job.k = opts->k;
+  job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
   job.cells = cells;
   job.level = level;
   for (int d = 0; d < 3; ++d) {

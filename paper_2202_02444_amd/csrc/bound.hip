@@ -102,7 +102,7 @@ __global__ __launch_bounds__(64, 1) void bound_kernel(NetDev net, BoundJob job) 
     const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass);
     if (valid && ch == 0) {
       float lo, hi;
-      enclose(o, lo, hi);
+      enclose(o, job.rigorous != 0, lo, hi);
       if (job.lo) job.lo[box] = lo;
       if (job.hi) job.hi[box] = hi;
       if (job.label) job.label[box] = (lo > 0.0f) ? (uint8_t)SPK_POSITIVE

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
         rid = -1;
       } else {
         float lo, hi;
-        enclose(o, lo, hi);
+        enclose(o, false, lo, hi);
         const bool safe = lo > 0.0f || hi < 0.0f;
         const float step = safe ? P.safety * sigma : 0.0f;
         sigma = safe ? sigma * P.eta_plus : sigma * P.eta_minus;

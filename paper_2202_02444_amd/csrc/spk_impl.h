@@ -41,6 +41,7 @@ struct BoundJob {
   int s;              // number of box axes (1..3)
   int policy;         // spk_policy (fixed or truncate)
   int k;              // kept terms (truncate)
+  int rigorous;       // 1: lo/hi use the rigorous rounding radius
   // IN_AABB: a = lo [n][3], b = hi [n][3]; IN_GENERAL: a = center [n][3], b = axes [n][s][3]
   const float* a;
   const float* b;

@@ -108,8 +108,11 @@ def _ptr(t, dtype=None, shape=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def opts(policy="truncate", k=31):
-    return BoundOpts(POLICY[policy], int(k), 0, 0)
+FLAG_RIGOROUS = 1
+
+
+def opts(policy="truncate", k=31, rigorous=False):
+    return BoundOpts(POLICY[policy], int(k), 0, FLAG_RIGOROUS if rigorous else 0)
 
 
 class Net:
@@ -182,10 +185,11 @@ def _aux(center=None, radius=None, err=None, slot_src=None):
                     _ptr(err, torch.float32, name="err"), _ptr(slot_src, torch.int16, name="slot_src"))
 
 
-def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="truncate", k=31, aux=None):
+def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="truncate", k=31, aux=None,
+                   rigorous=False):
     import torch
     n = box_lo.shape[0]
-    o = opts(policy, k)
+    o = opts(policy, k, rigorous)
     a = _aux(**aux) if aux else None
     st = lib().spk_classify_boxes(ctx.handle, net.handle, ctypes.byref(o), n,
                                   _ptr(box_lo, torch.float32, (n, 3), "box_lo"),
@@ -196,10 +200,10 @@ def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="tr
     _check(st, "spk_classify_boxes")
 
 
-def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=None):
+def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=None, rigorous=False):
     import torch
     n, s = axes.shape[0], axes.shape[1]
-    o = opts(policy, k)
+    o = opts(policy, k, rigorous)
     a = _aux(**aux) if aux else None
     st = lib().spk_range_bound(ctx.handle, net.handle, ctypes.byref(o), n, s,
                                _ptr(center, torch.float32, (n, 3), "center"),

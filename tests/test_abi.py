@@ -75,6 +75,9 @@ def test_bound_calls_validate_before_launch():
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(o), 4, None, FAKE, FAKE, None, None, None) == spk.E_INVAL
     assert L.spk_range_bound(FAKE, FAKE, ctypes.byref(o), 4, 4, FAKE, FAKE, FAKE, FAKE, None) == spk.E_INVAL
     assert L.spk_range_bound(FAKE, FAKE, ctypes.byref(o), 0, 3, None, None, None, None, None) == spk.OK
+    badflags = spk.BoundOpts(1, 31, 0, 8)
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(badflags), 4, FAKE, FAKE, FAKE, None, None,
+                                None) == spk.E_INVAL
     fx = spk.opts("fixed", 0)
     aux = spk.BoundAux(None, None, None, FAKE)
     assert L.spk_range_bound(FAKE, FAKE, ctypes.byref(fx), 4, 3, FAKE, FAKE, FAKE, FAKE,

@@ -2,15 +2,15 @@
 the C ABI.  Tolerance: raw endpoints (center -/+ radius, before the rounding
 inflation) within 1e-5 * S with S = max(|lo_o|, |hi_o|, RMS of f); labels
 equal unless the oracle bound is within the tolerance plus the GPU's
-rounding-error radius of zero; the inflated bound contains every sampled f."""
+floating-point margin of zero; the returned bound contains every sampled f."""
 import numpy as np
 import pytest
 
 import workloads as wl
 from oracle import mlp as omlp
 
-from parity import (TOL, endpoint_errors, gpu_classify, keep_sets_from_src, label_ambiguous, oracle_labels,
-                    s_net, soundness_violations)
+from parity import (TOL, default_margin, endpoint_errors, gpu_classify, keep_sets_from_src, label_ambiguous,
+                    oracle_labels, s_net, soundness_violations)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,8 +42,6 @@ def _run(ctx, net, lo, hi, policy, k, replay=True, sound_rng=None):
         c_r, r_r, lo_r, hi_r = omlp.bound_boxes(net, lo, hi, policy, k, keep_sets=sets, record=rec)
         res["replay"] = endpoint_errors(out["center"], out["radius"], lo_r, hi_r, S)
         res["replay_bounds"] = (lo_r, hi_r)
-        # every replayed selection is a valid top-k of the FP64 magnitudes within tolerance
-        c_f, r_f, _, _ = omlp.bound_boxes(net, lo, hi, policy, k)
         res["sets"] = sets
     if sound_rng is not None:
         res["violations"], _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], sound_rng)
@@ -57,7 +55,7 @@ def test_tiny_fixed(ctx):
     assert r["free"].max() <= TOL, r["free"].max()
     assert r["violations"] == 0
     lo_o, hi_o = r["oracle"][2], r["oracle"][3]
-    amb = label_ambiguous(lo_o, hi_o, r["S"], r["out"]["err"])
+    amb = label_ambiguous(lo_o, hi_o, r["S"], default_margin(r["out"]))
     lab_o = oracle_labels(lo_o, hi_o)
     assert np.array_equal(r["out"]["label"][~amb], lab_o[~amb])
     assert amb.mean() < 0.01
@@ -72,7 +70,7 @@ def test_tiny_truncate(ctx, k):
     assert (r["free"] <= TOL).mean() >= 0.99
     assert r["violations"] == 0
     lo_r, hi_r = r["replay_bounds"]
-    amb = label_ambiguous(lo_r, hi_r, r["S"], r["out"]["err"])
+    amb = label_ambiguous(lo_r, hi_r, r["S"], default_margin(r["out"]))
     assert np.array_equal(r["out"]["label"][~amb], oracle_labels(lo_r, hi_r)[~amb])
 
 
@@ -192,3 +190,19 @@ def test_eval_points(ctx):
         fo = omlp.forward(net, x)
         S = max(s_net(net), 1e-30)
         assert np.max(np.abs(f.cpu().numpy() - fo)) <= TOL * max(S, np.abs(fo).max())
+
+
+@pytest.mark.parametrize("H,depth,act", [(32, 2, "relu"), (64, 3, "elu"), (128, 2, "sin"), (256, 3, "relu")])
+def test_rigorous_mode_sound_and_reported(ctx, H, depth, act):
+    """SPK_FLAG_RIGOROUS: the a-priori rounding radius is added; the bound
+    contains every sampled f and contains the default bound's raw part."""
+    from paper_2202_02444_amd import spk
+    widths = [3] + [H] * depth + [1]
+    net = wl.siren_mlp(widths, 80 + H, 30.0) if act == "sin" else wl.he_normal_mlp(widths, 80 + H, act=act)
+    lo, hi = wl.boxes(256, 81, 1e-3, 0.25)
+    g = spk.Net.from_spec(net)
+    out = gpu_classify(ctx, g, lo, hi, "truncate", 31, rigorous=True)
+    bad, _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], np.random.default_rng(8))
+    assert bad == 0
+    assert np.all(out["lo"] <= out["center"] - out["radius"]) and np.all(out["hi"] >= out["center"] + out["radius"])
+    assert np.all(out["err"] > 0)
