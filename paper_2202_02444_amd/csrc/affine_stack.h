@@ -83,11 +83,15 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
       e[i] = (e[i] * omega0 + kU * (rs + yinf[i])) * kGrow + (float)(2.0 * kU64) * (float)fabs(xc[i]) + kEta;
     }
     const double x0 = xc[i];
-    float rY = 0.0f;
+    // the range radius is summed in FP64: the linearisation parameters of a
+    // narrow straddling neuron are sensitive to it
+    double rYd = 0.0;
 #pragma unroll
-    for (int C = 1; C < NG; ++C) rY += fabsf(y[i][C]);
-    const float r = rY + yinf[i];
-    const double xl = x0 - (double)r, xu = x0 + (double)r;
+    for (int C = 1; C < NG; ++C) rYd += (double)fabsf(y[i][C]);
+    const double rd = rYd + (double)yinf[i];
+    const float rY = round_up_f(rYd);
+    const float r = round_up_f(rd);
+    const double xl = x0 - rd, xu = x0 + rd;
     const ActOut p = act_params<ACT>(xl, xu, x0);
     const float alf = (float)p.al;
     // rounding of the range read-off (the FP32 sum r)
@@ -215,16 +219,16 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      float zi = yinf[i];
+      double zi = (double)yinf[i];
 #pragma unroll
       for (int C = 1; C < S::NS; ++C) {
         if ((freem >> C) & 1u) {
-          zi += fabsf(y[i][C]);
+          zi += (double)fabsf(y[i][C]);
           y[i][C] = (slot[i] == C) ? gam[i] : 0.0f;
         }
       }
-      zi += keepnew[i] ? 0.0f : gam[i];
-      yinf[i] = zi;
+      zi += keepnew[i] ? 0.0 : (double)gam[i];
+      yinf[i] = (float)zi;
     }
     if (rec != nullptr) {
       if (ch == 0) {
@@ -246,6 +250,85 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
     u[i] = ef + (cK * rnext[i] + cD * (float)fabs(xc[i])) * kGrowR;
   }
   return n_occ_new;
+}
+
+// Reduce the VALU partial sums of output tile tp of box b over the four
+// K-row groups of the wave and store them in the LDS vectors.
+template <class S>
+__device__ __forceinline__ void store_partials(LdsState<S>& sm, int b, int tp, int g, int c, float sx, float se,
+                                               double sd) {
+  sx += __shfl_xor(sx, 16, 64);
+  se += __shfl_xor(se, 16, 64);
+  sd += __shfl_xor(sd, 16, 64);
+  sx += __shfl_xor(sx, 32, 64);
+  se += __shfl_xor(se, 32, 64);
+  sd += __shfl_xor(sd, 32, 64);
+  if (g == 0) {
+    sm.vinf[b * S::H + 16 * tp + c] = sx;
+    sm.vu[b * S::H + 16 * tp + c] = se;
+    sm.vc[b * S::H + 16 * tp + c] = sd;
+  }
+}
+
+// Column tile n of every box of the wave through one H -> H layer (MFMA),
+// results written back over the tile.  The first pass also forms the FP64
+// center and the |W| products on VALU.
+template <class S, bool FIRST>
+__device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, int n, int lane) {
+  constexpr int H = S::H, MT = S::MT, BPW = S::BPW;
+  const int g = lane >> 4, c = lane & 15;
+  f4 acc[MT][BPW];
+  float px[MT][BPW], pe[MT][BPW];
+  double pd[MT][BPW];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      acc[tp][b] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+      if (FIRST) { px[tp][b] = 0.0f; pe[tp][b] = 0.0f; pd[tp][b] = 0.0; }
+    }
+  }
+#pragma unroll 1
+  for (int t = 0; t < MT; ++t) {
+    f4 w[MT];
+    const f4* Wt = Wl + (size_t)t * MT * 64 + lane;
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) w[tp] = Wt[tp * 64];
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      const f4 bfr = *(const f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * t + g)];
+      f4 vx, ve;
+      double vd[4];
+      if (FIRST) {
+        vx = *(const f4*)&sm.vinf[b * H + 16 * t + 4 * g];
+        ve = *(const f4*)&sm.vu[b * H + 16 * t + 4 * g];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vd[j] = sm.vc[b * H + 16 * t + 4 * g + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int tp = 0; tp < MT; ++tp) {
+          acc[tp][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[tp][j], bfr[j], acc[tp][b], 0, 0, 0);
+          if (FIRST) {
+            px[tp][b] = fmaf(fabsf(w[tp][j]), vx[j], px[tp][b]);
+            pe[tp][b] = fmaf(fabsf(w[tp][j]), ve[j], pe[tp][b]);
+            pd[tp][b] = fma((double)w[tp][j], vd[j], pd[tp][b]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+      if (FIRST) store_partials<S>(sm, b, tp, g, c, px[tp][b], pe[tp][b], pd[tp][b]);
+      *(f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * tp + g)] = acc[tp][b];
+    }
+  }
+  __syncthreads();
 }
 
 // One hidden layer (index a among the H -> H layers) from owner layout to
@@ -279,18 +362,19 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
   __syncthreads();
 
   // ---- generators on MFMA, center in FP64, |W| xinf and |W| u on VALU ----
-  f4 acc[MT][BPW * NT];
-  float px[MT][BPW], pe[MT][BPW];
-  double pd[MT][BPW];
-#pragma unroll
-  for (int tp = 0; tp < MT; ++tp) {
-#pragma unroll
-    for (int q = 0; q < BPW * NT; ++q) acc[tp][q] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int b = 0; b < BPW; ++b) { px[tp][b] = 0.0f; pe[tp][b] = 0.0f; pd[tp][b] = 0.0; }
-  }
   const f4* Wl = (const f4*)net.Wp + (size_t)a * (H * H / 4);
   if constexpr (BPW == 1) {
+    f4 acc[MT][NT];
+    float px[MT], pe[MT];
+    double pd[MT];
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[tp][n] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+      px[tp] = 0.0f;
+      pe[tp] = 0.0f;
+      pd[tp] = 0.0;
+    }
     // one box: stream the A fragments, each used by NT MFMAs right away
 #pragma unroll 1
     for (int t = 0; t < MT; ++t) {
@@ -311,71 +395,27 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
 #pragma unroll
           for (int n = 0; n < NT; ++n)
             acc[tp][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], bfr[n][j], acc[tp][n], 0, 0, 0);
-          px[tp][0] = fmaf(fabsf(w[j]), vx[j], px[tp][0]);
-          pe[tp][0] = fmaf(fabsf(w[j]), ve[j], pe[tp][0]);
-          pd[tp][0] = fma((double)w[j], vd[j], pd[tp][0]);
+          px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
+          pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
+          pd[tp] = fma((double)w[j], vd[j], pd[tp]);
         }
       }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+#pragma unroll
+      for (int n = 0; n < NT; ++n) *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = acc[tp][n];
     }
   } else {
-    // several boxes: hold this K block's A fragments for every output tile
-    // (MT is small here) and reuse them box after box, so only one box's B
-    // operands are live at a time
+    // several boxes: one 16-column tile at a time (fewer live accumulators);
+    // this K block's A fragments are held for every output tile (MT is small
+    // here) and reused box after box.  Column tile n is read only in pass n,
+    // so its outputs may overwrite it when the pass ends.
+    multi_box_pass<S, true>(sm, Wl, 0, lane);
 #pragma unroll 1
-    for (int t = 0; t < MT; ++t) {
-      f4 w[MT];
-      const f4* Wt = Wl + (size_t)t * MT * 64 + lane;
-#pragma unroll
-      for (int tp = 0; tp < MT; ++tp) w[tp] = Wt[tp * 64];
-#pragma unroll
-      for (int b = 0; b < BPW; ++b) {
-        f4 bfr[NT];
-#pragma unroll
-        for (int n = 0; n < NT; ++n) bfr[n] = *(const f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * t + g)];
-        const f4 vx = *(const f4*)&sm.vinf[b * H + 16 * t + 4 * g];
-        const f4 ve = *(const f4*)&sm.vu[b * H + 16 * t + 4 * g];
-        double vd[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) vd[j] = sm.vc[b * H + 16 * t + 4 * g + j];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-          for (int tp = 0; tp < MT; ++tp) {
-#pragma unroll
-            for (int n = 0; n < NT; ++n)
-              acc[tp][b * NT + n] =
-                  __builtin_amdgcn_mfma_f32_16x16x4f32(w[tp][j], bfr[n][j], acc[tp][b * NT + n], 0, 0, 0);
-            px[tp][b] = fmaf(fabsf(w[tp][j]), vx[j], px[tp][b]);
-            pe[tp][b] = fmaf(fabsf(w[tp][j]), ve[j], pe[tp][b]);
-            pd[tp][b] = fma((double)w[tp][j], vd[j], pd[tp][b]);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- MFMA layout -> LDS -> owner layout ----
-#pragma unroll
-  for (int tp = 0; tp < MT; ++tp) {
-#pragma unroll
-    for (int b = 0; b < BPW; ++b) {
-      float sx = px[tp][b], se = pe[tp][b];
-      double sd = pd[tp][b];
-      sx += __shfl_xor(sx, 16, 64);
-      se += __shfl_xor(se, 16, 64);
-      sd += __shfl_xor(sd, 16, 64);
-      sx += __shfl_xor(sx, 32, 64);
-      se += __shfl_xor(se, 32, 64);
-      sd += __shfl_xor(sd, 32, 64);
-      if (g == 0) {
-        sm.vinf[b * H + 16 * tp + c] = sx;
-        sm.vu[b * H + 16 * tp + c] = se;
-        sm.vc[b * H + 16 * tp + c] = sd;
-      }
-#pragma unroll
-      for (int n = 0; n < NT; ++n) *(f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * tp + g)] = acc[tp][b * NT + n];
-    }
+    for (int n = 1; n < NT; ++n) multi_box_pass<S, false>(sm, Wl, n, lane);
   }
   __syncthreads();
 #pragma unroll
@@ -430,15 +470,17 @@ __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double 
   p0 = seg_allsum_d<SEG>(p0);
   pinf = seg_allsum<SEG>(pinf);
   pu = seg_allsum<SEG>(pu);
-  float r = 0.0f;
+  double rd = 0.0;
 #pragma unroll
   for (int C = 1; C < NG; ++C) {
     float pc = wv[0] * y[0][C];
     pc = fmaf(wv[1], y[1][C], pc);
     pc = fmaf(wv[2], y[2][C], pc);
     pc = fmaf(wv[3], y[3][C], pc);
-    r += fabsf(seg_allsum<SEG>(pc));
+    rd += (double)fabsf(seg_allsum<SEG>(pc));
   }
+  rd += (double)pinf;
+  const float r = (float)rd;
 #pragma unroll
   for (int C = NG; C < NS; ++C) {
     float pc = wv[0] * y[0][C];
@@ -447,7 +489,6 @@ __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double 
     pc = fmaf(wv[3], y[3][C], pc);
     pass[C - NG] = seg_allsum<SEG>(pc) + net.bL;
   }
-  r += pinf;
   OutVals o;
   o.y0 = p0 + (double)net.bL;
   o.r = r;
