@@ -60,6 +60,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the octree / ray extra measurements")
     ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed region, one plain device-to-device copy of this many MiB "
+                         "(a known byte count that calibrates the HBM byte counters of a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
@@ -104,6 +107,14 @@ def main():
     value = args.boxes * args.steps / wall
     fl = algorithmic_flops_per_box() * args.boxes
     achieved = fl / (np.mean(kern_ms) * 1e-3)
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     labels = lab.cpu().numpy()
     out = {

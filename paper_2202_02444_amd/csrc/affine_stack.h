@@ -60,7 +60,7 @@ __device__ __forceinline__ float round_up_f(double v) {
 // + cD |x0| is the vector the next layer's rounding-error product |W| u needs.
 // Returns the new number of occupied generator slots.
 template <class S, int ACT, int POL, int NPASS>
-__device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], float (&yinf)[4], float (&e)[4],
+__device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
                                         float (&u)[4], int n_occ, int k, float cK, float cD, float omega0, int lane,
                                         int16_t* rec) {
   static_assert(NPASS == 0 || POL == SPK_AFFINE_FIXED, "passengers ride along affine-fixed passes only");
@@ -69,14 +69,14 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
-    for (int C = NG; C < S::NS; ++C) y[i][C] = act_point<ACT>(y[i][C], omega0);
+    for (int C = NG; C < S::NS; ++C) y[C][i] = act_point<ACT>(y[C][i], omega0);
     if (ACT == SPK_ACT_SIN) {
       // Table 2 constant multiplication by omega0 before sin
       float rs = 0.0f;
 #pragma unroll
       for (int C = 1; C < NG; ++C) {
-        y[i][C] *= omega0;
-        rs += fabsf(y[i][C]);
+        y[C][i] *= omega0;
+        rs += fabsf(y[C][i]);
       }
       yinf[i] *= omega0;
       xc[i] *= (double)omega0;
@@ -87,7 +87,7 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
     // narrow straddling neuron are sensitive to it
     double rYd = 0.0;
 #pragma unroll
-    for (int C = 1; C < NG; ++C) rYd += (double)fabsf(y[i][C]);
+    for (int C = 1; C < NG; ++C) rYd += (double)fabsf(y[C][i]);
     const double rd = rYd + (double)yinf[i];
     const float rY = round_up_f(rYd);
     const float r = round_up_f(rd);
@@ -109,9 +109,9 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
     float ep = fabsf(alf) * e[i] + (exact ? 0.0f : p.lip * ext + p.dg);
     const double z0 = fma(p.al, x0, p.be);
 #pragma unroll
-    for (int C = 1; C < NG; ++C) y[i][C] *= alf;
+    for (int C = 1; C < NG; ++C) y[C][i] *= alf;
     xc[i] = z0;
-    y[i][0] = (float)z0;
+    y[0][i] = (float)z0;
     const float zi = fabsf(alf) * yinf[i];
     // FP32 slope applied to the generators (2u: slope rounding + product),
     // condensed-term product, FP64 center update
@@ -139,7 +139,7 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
     kold[0] = 0u;
 #pragma unroll
     for (int C = 1; C < S::NS; ++C) {
-      const float mu = seg_allsum<SEG>((fabsf(y[0][C]) + fabsf(y[1][C])) + (fabsf(y[2][C]) + fabsf(y[3][C])));
+      const float mu = seg_allsum<SEG>((fabsf(y[C][0]) + fabsf(y[C][1])) + (fabsf(y[C][2]) + fabsf(y[C][3])));
       kold[C] = __float_as_uint(mu) & 0x7fffffffu;
     }
     uint32_t knew[4];
@@ -223,8 +223,8 @@ __device__ __forceinline__ int activate(double (&xc)[4], float (&y)[4][S::NS], f
 #pragma unroll
       for (int C = 1; C < S::NS; ++C) {
         if ((freem >> C) & 1u) {
-          zi += (double)fabsf(y[i][C]);
-          y[i][C] = (slot[i] == C) ? gam[i] : 0.0f;
+          zi += (double)fabsf(y[C][i]);
+          y[C][i] = (slot[i] == C) ? gam[i] : 0.0f;
         }
       }
       zi += keepnew[i] ? 0.0 : (double)gam[i];
@@ -270,9 +270,67 @@ __device__ __forceinline__ void store_partials(LdsState<S>& sm, int b, int tp, i
   }
 }
 
-// Column tile n of every box of the wave through one H -> H layer (MFMA),
-// results written back over the tile.  The first pass also forms the FP64
-// center and the |W| products on VALU.
+// Column tile n of the wave's single box (H = 256) through one H -> H layer.
+// The A fragments stream from L2 in MFMA order (fragment (t, tp) is the
+// q = t MT + tp th one); a ring of PF fragments keeps PF - 1 loads in flight
+// so their latency hides behind the MFMAs.  The first pass also forms the
+// FP64 center and the |W| products on VALU.
+template <class S, bool FIRST>
+__device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, int n, int lane) {
+  constexpr int MT = S::MT, PF = 4;
+  static_assert(S::BPW == 1 && MT % PF == 0, "one box per wave; the ring index repeats every K block");
+  const int g = lane >> 4, c = lane & 15;
+  f4 acc[MT];
+  float px[MT], pe[MT];
+  double pd[MT];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+    if (FIRST) { px[tp] = 0.0f; pe[tp] = 0.0f; pd[tp] = 0.0; }
+  }
+  const f4* Wq = Wl + lane;
+  f4 ring[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+#pragma unroll 1
+  for (int t = 0; t < MT; ++t) {
+    const f4 bfr = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * t + g)];
+    f4 vx, ve;
+    double vd[4];
+    if (FIRST) {
+      vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
+      ve = *(const f4*)&sm.vu[16 * t + 4 * g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
+    }
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      const f4 w = ring[tp % PF];
+      const int qn = min(t * MT + tp + PF, MT * MT - 1);   // past the end: a harmless reload
+      ring[tp % PF] = Wq[(size_t)qn * 64];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[tp] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], bfr[j], acc[tp], 0, 0, 0);
+        if (FIRST) {
+          px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
+          pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
+          pd[tp] = fma((double)w[j], vd[j], pd[tp]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    if (FIRST) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+    *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = acc[tp];
+  }
+  __syncthreads();
+}
+
+// Column tile n of every box of the wave (H < 256: several boxes) through one
+// H -> H layer.  This K block's A fragments are held for every output tile
+// (MT is small here) and reused box after box.
 template <class S, bool FIRST>
 __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, int n, int lane) {
   constexpr int H = S::H, MT = S::MT, BPW = S::BPW;
@@ -288,12 +346,19 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
       if (FIRST) { px[tp][b] = 0.0f; pe[tp][b] = 0.0f; pd[tp][b] = 0.0; }
     }
   }
+  // the next K block's A fragments load while this one's MFMAs run
+  f4 wn[MT];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) wn[tp] = Wl[(size_t)tp * 64 + lane];
 #pragma unroll 1
   for (int t = 0; t < MT; ++t) {
     f4 w[MT];
-    const f4* Wt = Wl + (size_t)t * MT * 64 + lane;
+    const f4* Wt = Wl + (size_t)min(t + 1, MT - 1) * MT * 64 + lane;
 #pragma unroll
-    for (int tp = 0; tp < MT; ++tp) w[tp] = Wt[tp * 64];
+    for (int tp = 0; tp < MT; ++tp) {
+      w[tp] = wn[tp];
+      wn[tp] = Wt[tp * 64];
+    }
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
       const f4 bfr = *(const f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * t + g)];
@@ -337,7 +402,7 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
 // error radius; passengers receive the bias too.
 template <class S, int NPASS>
 __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm, int a, double (&xc)[4],
-                                             float (&y)[4][S::NS], float (&yinf)[4], float (&e)[4],
+                                             f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
                                              const float (&u)[4], int lane) {
   constexpr int H = S::H, MT = S::MT, NT = S::NT, NS = S::NS, BPW = S::BPW, SEG = S::SEG;
   const int g = lane >> 4, c = lane & 15;
@@ -348,7 +413,7 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
   // ---- owner layout -> LDS ----
 #pragma unroll
   for (int C = 0; C < NS; ++C) {
-    f4 v = {y[0][C], y[1][C], y[2][C], y[3][C]};
+    const f4 v = y[C];
     *(f4*)&sm.tile[taddr<S>(bo, C, ch)] = v;
   }
   {
@@ -364,55 +429,10 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
   // ---- generators on MFMA, center in FP64, |W| xinf and |W| u on VALU ----
   const f4* Wl = (const f4*)net.Wp + (size_t)a * (H * H / 4);
   if constexpr (BPW == 1) {
-    f4 acc[MT][NT];
-    float px[MT], pe[MT];
-    double pd[MT];
-#pragma unroll
-    for (int tp = 0; tp < MT; ++tp) {
-#pragma unroll
-      for (int n = 0; n < NT; ++n) acc[tp][n] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
-      px[tp] = 0.0f;
-      pe[tp] = 0.0f;
-      pd[tp] = 0.0;
-    }
-    // one box: stream the A fragments, each used by NT MFMAs right away
+    single_box_pass<S, true>(sm, Wl, 0, lane);
 #pragma unroll 1
-    for (int t = 0; t < MT; ++t) {
-      f4 bfr[NT];
-#pragma unroll
-      for (int n = 0; n < NT; ++n) bfr[n] = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * t + g)];
-      const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
-      const f4 ve = *(const f4*)&sm.vu[16 * t + 4 * g];
-      double vd[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
-      const f4* Wt = Wl + (size_t)t * MT * 64 + lane;
-#pragma unroll
-      for (int tp = 0; tp < MT; ++tp) {
-        const f4 w = Wt[tp * 64];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-          for (int n = 0; n < NT; ++n)
-            acc[tp][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], bfr[n][j], acc[tp][n], 0, 0, 0);
-          px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
-          pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
-          pd[tp] = fma((double)w[j], vd[j], pd[tp]);
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int tp = 0; tp < MT; ++tp) {
-      store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
-#pragma unroll
-      for (int n = 0; n < NT; ++n) *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = acc[tp][n];
-    }
+    for (int n = 1; n < NT; ++n) single_box_pass<S, false>(sm, Wl, n, lane);
   } else {
-    // several boxes: one 16-column tile at a time (fewer live accumulators);
-    // this K block's A fragments are held for every output tile (MT is small
-    // here) and reused box after box.  Column tile n is read only in pass n,
-    // so its outputs may overwrite it when the pass ends.
     multi_box_pass<S, true>(sm, Wl, 0, lane);
 #pragma unroll 1
     for (int n = 1; n < NT; ++n) multi_box_pass<S, false>(sm, Wl, n, lane);
@@ -421,7 +441,7 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
 #pragma unroll
   for (int C = 1; C < NS; ++C) {
     const f4 v = *(const f4*)&sm.tile[taddr<S>(bo, C, ch)];
-    y[0][C] = v.x; y[1][C] = v.y; y[2][C] = v.z; y[3][C] = v.w;
+    y[C] = v;
   }
   {
     const f4 xi = *(const f4*)&sm.vinf[4 * lane];
@@ -432,9 +452,9 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       xc[i] = sm.vc[4 * lane + i] + (double)bh[i];
-      y[i][0] = (float)xc[i];
+      y[0][i] = (float)xc[i];
 #pragma unroll
-      for (int C = NS - NPASS; C < NS; ++C) y[i][C] += bh[i];
+      for (int C = NS - NPASS; C < NS; ++C) y[C][i] += bh[i];
       yinf[i] = xi[i];
       e[i] = eu[i] * grow + eb[i];
     }
@@ -452,7 +472,7 @@ struct OutVals {
 // (every lane of the segment gets the same values).  pass[] receives the
 // passengers' plain evaluations f(x).
 template <class S, int NPASS>
-__device__ __forceinline__ OutVals output_layer(const NetDev& net, const double (&xc)[4], const float (&y)[4][S::NS],
+__device__ __forceinline__ OutVals output_layer(const NetDev& net, const double (&xc)[4], const f4 (&y)[S::NS],
                                                 const float (&yinf)[4], const float (&u)[4], int lane,
                                                 float (&pass)[NPASS > 0 ? NPASS : 1]) {
   constexpr int NS = S::NS, SEG = S::SEG, NG = NS - NPASS;
@@ -473,20 +493,20 @@ __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double 
   double rd = 0.0;
 #pragma unroll
   for (int C = 1; C < NG; ++C) {
-    float pc = wv[0] * y[0][C];
-    pc = fmaf(wv[1], y[1][C], pc);
-    pc = fmaf(wv[2], y[2][C], pc);
-    pc = fmaf(wv[3], y[3][C], pc);
+    float pc = wv[0] * y[C][0];
+    pc = fmaf(wv[1], y[C][1], pc);
+    pc = fmaf(wv[2], y[C][2], pc);
+    pc = fmaf(wv[3], y[C][3], pc);
     rd += (double)fabsf(seg_allsum<SEG>(pc));
   }
   rd += (double)pinf;
   const float r = (float)rd;
 #pragma unroll
   for (int C = NG; C < NS; ++C) {
-    float pc = wv[0] * y[0][C];
-    pc = fmaf(wv[1], y[1][C], pc);
-    pc = fmaf(wv[2], y[2][C], pc);
-    pc = fmaf(wv[3], y[3][C], pc);
+    float pc = wv[0] * y[C][0];
+    pc = fmaf(wv[1], y[C][1], pc);
+    pc = fmaf(wv[2], y[C][2], pc);
+    pc = fmaf(wv[3], y[C][3], pc);
     pass[C - NG] = seg_allsum<SEG>(pc) + net.bL;
   }
   OutVals o;
@@ -519,7 +539,7 @@ template <class S, int NPASS>
 __device__ __forceinline__ void layer0_affine(const NetDev& net, int ch, const double (&cc)[3],
                                               const float (&ax)[3][3], const float (&ein)[3],
                                               const float (&pts)[NPASS > 0 ? NPASS : 1][3], double (&xc)[4],
-                                              float (&y)[4][S::NS], float (&yinf)[4], float (&e)[4]) {
+                                              f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4]) {
   constexpr int NG = S::NS - NPASS;
   const f4* W0 = (const f4*)net.W0;   // rows padded to 4 floats
 #pragma unroll
@@ -530,7 +550,7 @@ __device__ __forceinline__ void layer0_affine(const NetDev& net, int ch, const d
     xc[i] = fma((double)w.z, cc[2], fma((double)w.y, cc[1], fma((double)w.x, cc[0], (double)bb)));
     const float cmag = (float)(fabs((double)w.x * cc[0]) + fabs((double)w.y * cc[1]) + fabs((double)w.z * cc[2])) +
                        fabsf(bb);
-    y[i][0] = (float)xc[i];
+    y[0][i] = (float)xc[i];
     // generator columns 1..3 = W0 times the box axes; the rest start empty
     const float g0 = fmaf(w.z, ax[0][2], fmaf(w.y, ax[0][1], w.x * ax[0][0]));
     const float g1 = fmaf(w.z, ax[1][2], fmaf(w.y, ax[1][1], w.x * ax[1][0]));
@@ -538,15 +558,15 @@ __device__ __forceinline__ void layer0_affine(const NetDev& net, int ch, const d
     const float gmag = fabsf(w.x) * (fabsf(ax[0][0]) + fabsf(ax[1][0]) + fabsf(ax[2][0])) +
                        fabsf(w.y) * (fabsf(ax[0][1]) + fabsf(ax[1][1]) + fabsf(ax[2][1])) +
                        fabsf(w.z) * (fabsf(ax[0][2]) + fabsf(ax[1][2]) + fabsf(ax[2][2]));
-    y[i][1] = g0;
-    y[i][2] = g1;
-    y[i][3] = g2;
+    y[1][i] = g0;
+    y[2][i] = g1;
+    y[3][i] = g2;
 #pragma unroll
-    for (int C = 4; C < NG; ++C) y[i][C] = 0.0f;
+    for (int C = 4; C < NG; ++C) y[C][i] = 0.0f;
 #pragma unroll
     for (int C = NG; C < S::NS; ++C) {
       const int q = C - NG;
-      y[i][C] = fmaf(w.z, pts[q][2], fmaf(w.y, pts[q][1], fmaf(w.x, pts[q][0], bb)));
+      y[C][i] = fmaf(w.z, pts[q][2], fmaf(w.y, pts[q][1], fmaf(w.x, pts[q][0], bb)));
     }
     yinf[i] = 0.0f;
     e[i] = (net.c3 * gmag + (float)(8.0 * kU64) * cmag + fabsf(w.x) * ein[0] + fabsf(w.y) * ein[1] +

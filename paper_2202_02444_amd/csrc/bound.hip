@@ -88,7 +88,8 @@ __global__ __launch_bounds__(64, 1) void bound_kernel(NetDev net, BoundJob job) 
     float ax[3][3], ein[3], pts[1][3] = {{0.0f, 0.0f, 0.0f}};
     box_input(job, box, valid, cc, ax, ein);
     double xc[4];
-    float y[4][NS], yinf[4], e[4], u[4];
+    f4 y[NS];
+    float yinf[4], e[4], u[4];
     layer0_affine<S, 0>(net, ch, cc, ax, ein, pts, xc, y, yinf, e);
     int n_occ = job.s;
     for (int a = 0; a < L - 1; ++a) {

@@ -148,7 +148,8 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
       pts[1][a] = sp[a];
     }
     double xc[4];
-    float y[4][NS], yinf[4], e[4], u[4];
+    f4 y[NS];
+    float yinf[4], e[4], u[4];
     layer0_affine<S, NPASS>(net, ch, cc, ax, ein, pts, xc, y, yinf, e);
     for (int a = 0; a < L - 1; ++a) {
       activate<S, ACT, SPK_AFFINE_FIXED, NPASS>(xc, y, yinf, e, u, 1, 0, net.cK, net.cD, net.omega0, lane,

@@ -201,17 +201,28 @@ def test_eval_points(ctx):
         assert np.max(np.abs(f.cpu().numpy() - fo)) <= TOL * max(S, np.abs(fo).max())
 
 
-@pytest.mark.parametrize("H,depth,act", [(32, 2, "relu"), (64, 3, "elu"), (128, 2, "sin"), (256, 3, "relu")])
-def test_rigorous_mode_sound_and_reported(ctx, H, depth, act):
-    """SPK_FLAG_RIGOROUS: the a-priori rounding radius is added; the bound
-    contains every sampled f and contains the default bound's raw part."""
+@pytest.mark.parametrize("act", ["relu", "elu", "sin"])
+@pytest.mark.parametrize("H", [32, 64, 128, 256])
+def test_rigorous_mode_every_kernel(ctx, act, H):
+    """SPK_FLAG_RIGOROUS on every kernel instantiation (fixed, truncate k = 15
+    with 16 term slots, k = 31 with 32): the bound adds the a-priori rounding
+    radius, which is positive and finite, contains the raw bound and every
+    sampled f; the raw bound still matches the oracle."""
+    widths = [3] + [H] * 3 + [1]
+    net = wl.siren_mlp(widths, 90 + H, 30.0) if act == "sin" else wl.he_normal_mlp(widths, 90 + H, act=act)
+    lo, hi = wl.boxes(128, 91, 1e-3, 0.25)
     from paper_2202_02444_amd import spk
-    widths = [3] + [H] * depth + [1]
-    net = wl.siren_mlp(widths, 80 + H, 30.0) if act == "sin" else wl.he_normal_mlp(widths, 80 + H, act=act)
-    lo, hi = wl.boxes(256, 81, 1e-3, 0.25)
     g = spk.Net.from_spec(net)
-    out = gpu_classify(ctx, g, lo, hi, "truncate", 31, rigorous=True)
-    bad, _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], np.random.default_rng(8))
-    assert bad == 0
-    assert np.all(out["lo"] <= out["center"] - out["radius"]) and np.all(out["hi"] >= out["center"] + out["radius"])
-    assert np.all(out["err"] > 0)
+    for policy, k in (("fixed", 0), ("truncate", 15), ("truncate", 31)):
+        out = gpu_classify(ctx, g, lo, hi, policy, k, want_src=(policy == "truncate"), rigorous=True)
+        bad, _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], np.random.default_rng(8))
+        assert bad == 0, (policy, k)
+        assert np.all(np.isfinite(out["err"])) and np.all(out["err"] > 0), (policy, k)
+        assert np.all(out["lo"] <= out["center"] - out["radius"]) and np.all(out["hi"] >= out["center"] + out["radius"])
+        if policy == "truncate":
+            sets = keep_sets_from_src(out["src"], 3, k, H)
+            lo_o, hi_o = omlp.bound_boxes(net, lo, hi, policy, k, keep_sets=sets)[2:]
+        else:
+            lo_o, hi_o = omlp.bound_boxes(net, lo, hi, policy, k)[2:]
+        S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+        assert endpoint_errors(out["center"], out["radius"], lo_o, hi_o, S).max() <= TOL, (policy, k)
