@@ -118,8 +118,9 @@ spk_status spk_ctx_sync(spk_ctx* ctx);
  * Optional diagnostic outputs of the bound calls (all dev, nullable).
  *   center, radius  [n]: the raw bound before rounding inflation,
  *                   lo_raw = center - radius, hi_raw = center + radius.
- *   err             [n]: the a-priori rigorous rounding-error radius (used for
- *                   lo/hi only under SPK_FLAG_RIGOROUS).
+ *   err             [n]: the widening applied beyond the raw bound: the
+ *                   a-priori rigorous rounding-error radius under
+ *                   SPK_FLAG_RIGOROUS, else the tolerance margin.
  *   slot_src        [n_linear-1][n][32] int16: for affine-truncate, after
  *                   each activation (n_linear-1 of them) and for each of the
  *                   32 term slots of each box: -1 the slot kept its previous

@@ -270,14 +270,19 @@ __device__ __forceinline__ void store_partials(LdsState<S>& sm, int b, int tp, i
   }
 }
 
+// VALU work that rides along an MFMA pass: none (later column tiles), the
+// FP64 center and |W| xinf (VA_CENTER), plus the rounding-error product |W| u
+// of the rigorous mode (VA_RIGOROUS).
+enum { VA_NONE = 0, VA_CENTER = 1, VA_RIGOROUS = 2 };
+
 // Column tile n of the wave's single box (H = 256) through one H -> H layer.
 // The A fragments stream from L2 in MFMA order (fragment (t, tp) is the
 // q = t MT + tp th one); a ring of PF fragments keeps PF - 1 loads in flight
-// so their latency hides behind the MFMAs.  The first pass also forms the
-// FP64 center and the |W| products on VALU.
-template <class S, bool FIRST>
+// so their latency hides behind the MFMAs, and the next K block's B fragment
+// and vectors are read from LDS one block ahead.
+template <class S, int VA>
 __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, int n, int lane) {
-  constexpr int MT = S::MT, PF = 4;
+  constexpr int MT = S::MT, PF = 8;
   static_assert(S::BPW == 1 && MT % PF == 0, "one box per wave; the ring index repeats every K block");
   const int g = lane >> 4, c = lane & 15;
   f4 acc[MT];
@@ -286,22 +291,36 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
     acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
-    if (FIRST) { px[tp] = 0.0f; pe[tp] = 0.0f; pd[tp] = 0.0; }
+    px[tp] = 0.0f;
+    pe[tp] = 0.0f;
+    pd[tp] = 0.0;
   }
   const f4* Wq = Wl + lane;
   f4 ring[PF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+  f4 bn = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, g)];
+  f4 xn = {0.0f, 0.0f, 0.0f, 0.0f}, en = {0.0f, 0.0f, 0.0f, 0.0f};
+  double dn[4] = {0.0, 0.0, 0.0, 0.0};
+  if (VA != VA_NONE) {
+    xn = *(const f4*)&sm.vinf[4 * g];
+    if (VA == VA_RIGOROUS) en = *(const f4*)&sm.vu[4 * g];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dn[j] = sm.vc[4 * g + j];
+  }
 #pragma unroll 1
   for (int t = 0; t < MT; ++t) {
-    const f4 bfr = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * t + g)];
-    f4 vx, ve;
+    const f4 bfr = bn, vx = xn, ve = en;
     double vd[4];
-    if (FIRST) {
-      vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
-      ve = *(const f4*)&sm.vu[16 * t + 4 * g];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
+    for (int j = 0; j < 4; ++j) vd[j] = dn[j];
+    const int t1 = min(t + 1, MT - 1);
+    bn = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * t1 + g)];
+    if (VA != VA_NONE) {
+      xn = *(const f4*)&sm.vinf[16 * t1 + 4 * g];
+      if (VA == VA_RIGOROUS) en = *(const f4*)&sm.vu[16 * t1 + 4 * g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dn[j] = sm.vc[16 * t1 + 4 * g + j];
     }
 #pragma unroll
     for (int tp = 0; tp < MT; ++tp) {
@@ -311,18 +330,18 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         acc[tp] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], bfr[j], acc[tp], 0, 0, 0);
-        if (FIRST) {
+        if (VA != VA_NONE) {
           px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
-          pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
           pd[tp] = fma((double)w[j], vd[j], pd[tp]);
         }
+        if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
       }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
-    if (FIRST) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+    if (VA != VA_NONE) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
     *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = acc[tp];
   }
   __syncthreads();
@@ -331,7 +350,7 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
 // Column tile n of every box of the wave (H < 256: several boxes) through one
 // H -> H layer.  This K block's A fragments are held for every output tile
 // (MT is small here) and reused box after box.
-template <class S, bool FIRST>
+template <class S, int VA>
 __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, int n, int lane) {
   constexpr int H = S::H, MT = S::MT, BPW = S::BPW;
   const int g = lane >> 4, c = lane & 15;
@@ -343,7 +362,9 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
       acc[tp][b] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
-      if (FIRST) { px[tp][b] = 0.0f; pe[tp][b] = 0.0f; pd[tp][b] = 0.0; }
+      px[tp][b] = 0.0f;
+      pe[tp][b] = 0.0f;
+      pd[tp][b] = 0.0;
     }
   }
   // the next K block's A fragments load while this one's MFMAs run
@@ -362,11 +383,11 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
       const f4 bfr = *(const f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * t + g)];
-      f4 vx, ve;
-      double vd[4];
-      if (FIRST) {
+      f4 vx = {0.0f, 0.0f, 0.0f, 0.0f}, ve = {0.0f, 0.0f, 0.0f, 0.0f};
+      double vd[4] = {0.0, 0.0, 0.0, 0.0};
+      if (VA != VA_NONE) {
         vx = *(const f4*)&sm.vinf[b * H + 16 * t + 4 * g];
-        ve = *(const f4*)&sm.vu[b * H + 16 * t + 4 * g];
+        if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[b * H + 16 * t + 4 * g];
 #pragma unroll
         for (int j = 0; j < 4; ++j) vd[j] = sm.vc[b * H + 16 * t + 4 * g + j];
       }
@@ -375,11 +396,11 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
 #pragma unroll
         for (int tp = 0; tp < MT; ++tp) {
           acc[tp][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[tp][j], bfr[j], acc[tp][b], 0, 0, 0);
-          if (FIRST) {
+          if (VA != VA_NONE) {
             px[tp][b] = fmaf(fabsf(w[tp][j]), vx[j], px[tp][b]);
-            pe[tp][b] = fmaf(fabsf(w[tp][j]), ve[j], pe[tp][b]);
             pd[tp][b] = fma((double)w[tp][j], vd[j], pd[tp][b]);
           }
+          if (VA == VA_RIGOROUS) pe[tp][b] = fmaf(fabsf(w[tp][j]), ve[j], pe[tp][b]);
         }
       }
     }
@@ -389,7 +410,7 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
   for (int tp = 0; tp < MT; ++tp) {
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
-      if (FIRST) store_partials<S>(sm, b, tp, g, c, px[tp][b], pe[tp][b], pd[tp][b]);
+      if (VA != VA_NONE) store_partials<S>(sm, b, tp, g, c, px[tp][b], pe[tp][b], pd[tp][b]);
       *(f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * tp + g)] = acc[tp][b];
     }
   }
@@ -403,7 +424,7 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
 template <class S, int NPASS>
 __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm, int a, double (&xc)[4],
                                              f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
-                                             const float (&u)[4], int lane) {
+                                             const float (&u)[4], int lane, bool rigorous) {
   constexpr int H = S::H, MT = S::MT, NT = S::NT, NS = S::NS, BPW = S::BPW, SEG = S::SEG;
   const int g = lane >> 4, c = lane & 15;
   const int bo = lane / SEG;
@@ -429,13 +450,19 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
   // ---- generators on MFMA, center in FP64, |W| xinf and |W| u on VALU ----
   const f4* Wl = (const f4*)net.Wp + (size_t)a * (H * H / 4);
   if constexpr (BPW == 1) {
-    single_box_pass<S, true>(sm, Wl, 0, lane);
+    if (rigorous)
+      single_box_pass<S, VA_RIGOROUS>(sm, Wl, 0, lane);
+    else
+      single_box_pass<S, VA_CENTER>(sm, Wl, 0, lane);
 #pragma unroll 1
-    for (int n = 1; n < NT; ++n) single_box_pass<S, false>(sm, Wl, n, lane);
+    for (int n = 1; n < NT; ++n) single_box_pass<S, VA_NONE>(sm, Wl, n, lane);
   } else {
-    multi_box_pass<S, true>(sm, Wl, 0, lane);
+    if (rigorous)
+      multi_box_pass<S, VA_RIGOROUS>(sm, Wl, 0, lane);
+    else
+      multi_box_pass<S, VA_CENTER>(sm, Wl, 0, lane);
 #pragma unroll 1
-    for (int n = 1; n < NT; ++n) multi_box_pass<S, false>(sm, Wl, n, lane);
+    for (int n = 1; n < NT; ++n) multi_box_pass<S, VA_NONE>(sm, Wl, n, lane);
   }
   __syncthreads();
 #pragma unroll
@@ -521,8 +548,12 @@ __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double 
 // w is the rigorous rounding radius err (rigorous = true) or the
 // floating-point tolerance margin 2^-18 (|center| + radius).  Non-finite
 // results become [-inf, +inf].
+__device__ __forceinline__ double tolerance_margin(const OutVals& o) {
+  return 3.814697265625e-06 * (fabs(o.y0) + (double)o.r) + 1e-30;
+}
+
 __device__ __forceinline__ void enclose(const OutVals& o, bool rigorous, float& lo, float& hi) {
-  const double margin = rigorous ? (double)o.err : 3.814697265625e-06 * (fabs(o.y0) + (double)o.r) + 1e-30;
+  const double margin = rigorous ? (double)o.err : tolerance_margin(o);
   const double s = ((double)o.r + margin) * (1.0 + 4.0 * kU64);
   lo = round_down_f(o.y0 - s);
   hi = round_up_f(o.y0 + s);

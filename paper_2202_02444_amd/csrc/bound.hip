@@ -97,7 +97,7 @@ __global__ __launch_bounds__(64, 1) void bound_kernel(NetDev net, BoundJob job) 
       if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
       n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, net.cK, net.cD, net.omega0, lane, rec);
       if (a == L - 2) break;
-      hidden_layer<S, 0>(net, sm, a, xc, y, yinf, e, u, lane);
+      hidden_layer<S, 0>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
     }
     float pass[1];
     const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(64, 1) void bound_kernel(NetDev net, BoundJob job) 
                                       : (hi < 0.0f) ? (uint8_t)SPK_NEGATIVE : (uint8_t)SPK_UNKNOWN;
       if (job.center) job.center[box] = (float)o.y0;
       if (job.radius) job.radius[box] = o.r;
-      if (job.err) job.err[box] = o.err;
+      if (job.err) job.err[box] = job.rigorous ? o.err : round_up_f(tolerance_margin(o));
     }
   }
 }

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
       activate<S, ACT, SPK_AFFINE_FIXED, NPASS>(xc, y, yinf, e, u, 1, 0, net.cK, net.cD, net.omega0, lane,
                                                   nullptr);
       if (a == L - 2) break;
-      hidden_layer<S, NPASS>(net, sm, a, xc, y, yinf, e, u, lane);
+      hidden_layer<S, NPASS>(net, sm, a, xc, y, yinf, e, u, lane, false);
     }
     float pass[NPASS];
     const OutVals o = output_layer<S, NPASS>(net, xc, y, yinf, u, lane, pass);

@@ -59,6 +59,9 @@ def test_tiny_fixed(ctx):
     lab_o = oracle_labels(lo_o, hi_o)
     assert np.array_equal(r["out"]["label"][~amb], lab_o[~amb])
     assert amb.mean() < 0.01
+    # default mode: the reported widening is the tolerance margin 2^-18 (|c| + r)
+    m = 3.814697265625e-06 * (np.abs(r["out"]["center"]) + r["out"]["radius"])
+    assert np.allclose(r["out"]["err"], m, rtol=1e-5, atol=1e-30)
 
 
 @pytest.mark.parametrize("k", [8, 16, 31])
