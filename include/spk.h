@@ -204,6 +204,28 @@ typedef struct {
 spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params* params, int64_t n,
                          const float* origin, const float* dir, float* t_hit, int32_t* iters);
 
+/*
+ * spk_closest_point: closest point on the level set f = 0 (Section 4.10) for
+ * n query points q dev [n][3] (n < 2^32).  The octree of `tree` is searched
+ * down to tree->max_level; cells are classified with `opts` (the paper uses
+ * affine-fixed).  A cell spans the level set when it is UNKNOWN and f takes
+ * both signs on its six face centers; it then contains a zero of f, so the
+ * farthest distance from q to it bounds the distance to the surface.  Result
+ * for query i: the center of a spanning cell (reached through UNKNOWN
+ * ancestors) minimising that farthest distance.
+ *   point  dev [n][3]: the cell center; NaN when no cell spans the surface.
+ *   dist   dev [n] nullable: |point - q|, +inf when none.
+ *   bound  dev [n] nullable: the farthest distance from q to that cell (an
+ *          upper bound of the distance from q to the surface), +inf when none.
+ * The call runs one round per level and waits for each round (it returns with
+ * the stream synchronized); it allocates its frontier buffers in device
+ * memory and frees them before returning (SPK_E_NOMEM beyond the context's
+ * workspace limit).
+ */
+spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                             const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,
+                             float* bound);
+
 /* Point evaluation f(x) for x dev [n][3] -> f dev [n] (FP32). */
 spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f);
 

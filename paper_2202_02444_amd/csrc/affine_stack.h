@@ -425,8 +425,7 @@ template <class S, int NPASS>
 __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm, int a, double (&xc)[4],
                                              f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
                                              const float (&u)[4], int lane, bool rigorous) {
-  constexpr int H = S::H, MT = S::MT, NT = S::NT, NS = S::NS, BPW = S::BPW, SEG = S::SEG;
-  const int g = lane >> 4, c = lane & 15;
+  constexpr int H = S::H, NT = S::NT, NS = S::NS, BPW = S::BPW, SEG = S::SEG;
   const int bo = lane / SEG;
   const int ch = lane % SEG;
   const float cK = net.cK;

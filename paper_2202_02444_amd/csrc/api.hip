@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "spk_impl.h"
@@ -138,7 +139,7 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   void* blk = nullptr;
   if (hipMalloc(&blk, total) != hipSuccess) { delete net; return SPK_E_NOMEM; }
   if (hipMemcpy(blk, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(blk);
+    (void)hipFree(blk);
     delete net;
     return SPK_E_DEVICE;
   }
@@ -213,7 +214,7 @@ static spk_status ctx_scratch(spk_ctx* ctx, size_t bytes, void** p) {
     if (ctx->workspace_limit && bytes > ctx->workspace_limit) return SPK_E_NOMEM;
     if (ctx->scratch) {
       if (hipStreamSynchronize(ctx->stream) != hipSuccess) return SPK_E_DEVICE;
-      hipFree(ctx->scratch);
+      (void)hipFree(ctx->scratch);
       ctx->scratch = nullptr;
       ctx->scratch_bytes = 0;
     }
@@ -342,6 +343,137 @@ spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params*
   spk_status st = ctx_scratch(ctx, 256, &counter);
   if (st != SPK_OK) return st;
   return launch_rays(net, p, n, origin, dir, t_hit, iters, (unsigned long long*)counter, ctx->stream, ctx->num_cus);
+}
+
+namespace {
+// Device buffers owned by one closest-point call.
+struct CallBuffers {
+  std::vector<std::pair<void**, size_t>> held;
+  size_t total = 0;
+  size_t limit = 0;
+  hipStream_t stream = nullptr;
+  ~CallBuffers() {
+    // kernels of the call may still use the buffers on an error return
+    (void)hipStreamSynchronize(stream);
+    for (auto& h : held)
+      if (*h.first) (void)hipFree(*h.first);
+  }
+  // (Re)allocate *p to at least `bytes`; contents are not kept.
+  spk_status ensure(void** p, size_t& cap, size_t bytes) {
+    if (bytes <= cap) return SPK_OK;
+    const size_t want = bytes + bytes / 2;
+    if (limit && total - cap + want > limit) return SPK_E_NOMEM;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    total -= cap;
+    cap = 0;
+    if (hipMalloc(p, want) != hipSuccess) return SPK_E_NOMEM;
+    cap = want;
+    total += want;
+    bool known = false;
+    for (auto& h : held) known = known || h.first == p;
+    if (!known) held.push_back({p, 0});
+    return SPK_OK;
+  }
+};
+}  // namespace
+
+spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                             const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,
+                             float* bound) {
+  if (ctx == nullptr || net == nullptr || tree == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
+  if (st != SPK_OK) return st;
+  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
+  if (tree->max_level < 0 || tree->max_level > 20) return SPK_E_INVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
+      return SPK_E_INVAL;
+  if (n < 0 || n > (int64_t)0xffffffffLL) return SPK_E_INVAL;
+  if (n == 0) return SPK_OK;
+  if (q == nullptr || point == nullptr) return SPK_E_INVAL;
+
+  CallBuffers B;
+  B.limit = ctx->workspace_limit;
+  B.stream = ctx->stream;
+  void *best = nullptr, *codes = nullptr, *qidx = nullptr, *ncodes = nullptr, *nqidx = nullptr, *labels = nullptr,
+       *fpts = nullptr, *fvals = nullptr, *cnt = nullptr;
+  size_t c_best = 0, c_codes = 0, c_qidx = 0, c_ncodes = 0, c_nqidx = 0, c_labels = 0, c_fpts = 0, c_fvals = 0,
+         c_cnt = 0;
+#define SPK_ENSURE(ptr, cap, bytes)                 \
+  do {                                              \
+    spk_status e_ = B.ensure(&(ptr), cap, (bytes)); \
+    if (e_ != SPK_OK) return e_;                    \
+  } while (0)
+  SPK_ENSURE(best, c_best, (size_t)n * 4);
+  SPK_ENSURE(codes, c_codes, (size_t)n * 8);
+  SPK_ENSURE(qidx, c_qidx, (size_t)n * 4);
+  SPK_ENSURE(cnt, c_cnt, 256);
+  st = launch_cp_init(n, (uint64_t*)codes, (uint32_t*)qidx, (unsigned*)best, point, ctx->stream, ctx->num_cus);
+  if (st != SPK_OK) return st;
+  int64_t m = n;
+  for (int level = 0; level <= tree->max_level && m > 0; ++level) {
+    const bool at_max = level == tree->max_level;
+    SPK_ENSURE(labels, c_labels, (size_t)m);
+    SPK_ENSURE(fpts, c_fpts, (size_t)m * 18 * 4);
+    SPK_ENSURE(fvals, c_fvals, (size_t)m * 6 * 4);
+    if (!at_max) {
+      SPK_ENSURE(ncodes, c_ncodes, (size_t)m * 8 * 8);
+      SPK_ENSURE(nqidx, c_nqidx, (size_t)m * 8 * 4);
+    }
+    BoundJob job = {};
+    job.n = m;
+    job.mode = IN_CELL;
+    job.s = 3;
+    job.policy = opts->policy;
+    job.k = opts->k;
+    job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
+    job.cells = (const uint64_t*)codes;
+    job.level = level;
+    for (int d = 0; d < 3; ++d) {
+      job.dom_lo[d] = tree->dom_lo[d];
+      job.dom_hi[d] = tree->dom_hi[d];
+    }
+    job.label = (uint8_t*)labels;
+    st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+    CpLevel L = {};
+    L.m = m;
+    L.level = level;
+    L.at_max = at_max ? 1 : 0;
+    for (int d = 0; d < 3; ++d) {
+      L.dom_lo[d] = tree->dom_lo[d];
+      L.dom_hi[d] = tree->dom_hi[d];
+    }
+    L.codes = (const uint64_t*)codes;
+    L.qidx = (const uint32_t*)qidx;
+    L.label = (const uint8_t*)labels;
+    L.q = q;
+    L.best = (unsigned*)best;
+    L.point = point;
+    L.fpts = (float*)fpts;
+    L.fvals = (float*)fvals;
+    L.ncodes = (uint64_t*)ncodes;
+    L.nqidx = (uint32_t*)nqidx;
+    L.ncount = (unsigned long long*)cnt;
+    L.cap = at_max ? 0 : m * 8;
+    st = launch_cp_round(net, L, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+    if (at_max) break;
+    unsigned long long next = 0ull;
+    if (hipMemcpyAsync(&next, cnt, sizeof(next), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return SPK_E_DEVICE;
+    m = (int64_t)next;   // at most 8 m by construction
+    std::swap(codes, ncodes);
+    std::swap(c_codes, c_ncodes);
+    std::swap(qidx, nqidx);
+    std::swap(c_qidx, c_nqidx);
+  }
+#undef SPK_ENSURE
+  st = launch_cp_finish(n, q, (const unsigned*)best, point, dist, bound, ctx->stream, ctx->num_cus);
+  if (st != SPK_OK) return st;
+  return check_hip(hipStreamSynchronize(ctx->stream));
 }
 
 spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f) {

@@ -44,20 +44,7 @@ __device__ __forceinline__ void box_input(const BoundJob& job, int64_t box, bool
 #pragma unroll
     for (int d = 0; d < 3; ++d) { lo[d] = job.a[3 * box + d]; hi[d] = job.b[3 * box + d]; }
   } else {
-    // Morton cell at job.level: de-interleave the x, y, z indices
-    const uint64_t code = job.cells[box];
-    uint32_t idx[3] = {0u, 0u, 0u};
-    for (int bb = 0; bb < job.level; ++bb) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) idx[d] |= (uint32_t)((code >> (3 * bb + d)) & 1ull) << bb;
-    }
-    const float scale = 1.0f / (float)(1u << job.level);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float size = (job.dom_hi[d] - job.dom_lo[d]) * scale;
-      lo[d] = job.dom_lo[d] + (float)idx[d] * size;
-      hi[d] = job.dom_lo[d] + (float)(idx[d] + 1u) * size;
-    }
+    cell_box(job.cells[box], job.level, job.dom_lo, job.dom_hi, lo, hi);
   }
   // center and half-width of the FP32 box, exactly, in FP64 (Procedure 3:
   // x_c = (x_l + x_u)/2, v = x_u - x_c); the half-width is then rounded to

@@ -60,6 +60,46 @@ struct BoundJob {
   int16_t* slot_src;
 };
 
+// FP32 bounds of the octree cell with Morton code `code` at `level` (bit b of
+// the x index at bit 3b, y at 3b+1, z at 3b+2) over the domain box.
+__device__ __forceinline__ void cell_box(uint64_t code, int level, const float (&dom_lo)[3],
+                                         const float (&dom_hi)[3], float (&lo)[3], float (&hi)[3]) {
+  uint32_t idx[3] = {0u, 0u, 0u};
+  for (int bb = 0; bb < level; ++bb) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) idx[d] |= (uint32_t)((code >> (3 * bb + d)) & 1ull) << bb;
+  }
+  const float scale = 1.0f / (float)(1u << level);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float size = (dom_hi[d] - dom_lo[d]) * scale;
+    lo[d] = dom_lo[d] + (float)idx[d] * size;
+    hi[d] = dom_lo[d] + (float)(idx[d] + 1u) * size;
+  }
+}
+
+// One round of the closest-point search (closest.hip): the frontier of
+// (query, cell) pairs at `level` and its outputs.
+struct CpLevel {
+  int64_t m;                 // frontier items
+  int level;
+  int at_max;                // 1: no children
+  float dom_lo[3];
+  float dom_hi[3];
+  const uint64_t* codes;     // [m] cells
+  const uint32_t* qidx;      // [m] query of each cell
+  const uint8_t* label;      // [m] classification of each cell
+  const float* q;            // [n][3] queries
+  unsigned* best;            // [n] distance bounds (float bits)
+  float* point;              // [n][3] candidates
+  float* fpts;               // [6m][3] face centers
+  float* fvals;              // [6m] f at the face centers
+  uint64_t* ncodes;          // [cap] next frontier
+  uint32_t* nqidx;           // [cap]
+  unsigned long long* ncount;
+  int64_t cap;
+};
+
 }  // namespace spk
 
 struct spk_net {
@@ -91,4 +131,9 @@ spk_status launch_eval(const spk_net* net, int64_t n, const float* x, float* f, 
 spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, const float* origin,
                        const float* dir, float* t_hit, int32_t* iters, unsigned long long* counter,
                        hipStream_t stream, int num_cus);
+spk_status launch_cp_init(int64_t n, uint64_t* codes, uint32_t* qidx, unsigned* best, float* point,
+                          hipStream_t stream, int num_cus);
+spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t stream, int num_cus);
+spk_status launch_cp_finish(int64_t n, const float* q, const unsigned* best, float* point, float* dist,
+                            float* best_out, hipStream_t stream, int num_cus);
 }  // namespace spk

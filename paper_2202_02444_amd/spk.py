@@ -22,7 +22,7 @@ UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
-           "spk_subdivide_frontier", "spk_cast_rays", "spk_eval_points")
+           "spk_subdivide_frontier", "spk_cast_rays", "spk_eval_points", "spk_closest_point")
 
 
 class BoundOpts(ctypes.Structure):
@@ -75,6 +75,8 @@ def lib():
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
         L.spk_eval_points.argtypes = [vp, vp, i64, vp, vp]
+        L.spk_closest_point.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i64, vp, vp,
+                                        vp, vp]
         for name in EXPORTS:
             if name not in ("spk_status_str", "spk_version"):
                 getattr(L, name).restype = ctypes.c_int
@@ -245,6 +247,19 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
                              _ptr(direction, torch.float32, (n, 3), "direction"),
                              _ptr(t_hit, torch.float32, (n,), "t_hit"), _ptr(iters, torch.int32, (n,), "iters"))
     _check(st, "spk_cast_rays")
+
+
+def closest_point(ctx, net, q, point, dist=None, bound=None, max_level=8, policy="fixed", k=31,
+                  dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), rigorous=False):
+    """spk_closest_point: point [n, 3], dist [n] and bound [n] for queries q [n, 3]."""
+    import torch
+    n = q.shape[0]
+    tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), 8)
+    o = opts(policy, k, rigorous)
+    st = lib().spk_closest_point(ctx.handle, net.handle, ctypes.byref(o), ctypes.byref(tp), n,
+                                 _ptr(q, torch.float32, (n, 3), "q"), _ptr(point, torch.float32, (n, 3), "point"),
+                                 _ptr(dist, torch.float32, (n,), "dist"), _ptr(bound, torch.float32, (n,), "bound"))
+    _check(st, "spk_closest_point")
 
 
 def eval_points(ctx, net, x, f):

@@ -106,3 +106,22 @@ def test_tree_and_ray_validation():
     assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp_bad), 4, FAKE, FAKE, FAKE, None) == spk.E_INVAL
     rp_bad2 = spk.ray_params(eta_minus=1.5)
     assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp_bad2), 4, FAKE, FAKE, FAKE, None) == spk.E_INVAL
+
+
+def test_closest_point_validation():
+    L = spk.lib()
+    o = spk.opts("fixed", 0)
+    tp = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8)
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 0, None, None, None, None) == spk.OK
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), -1, FAKE, FAKE, None, None) == spk.E_INVAL
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 4, None, FAKE, None, None) == spk.E_INVAL
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(o), None, 4, FAKE, FAKE, None, None) == spk.E_INVAL
+    tp_deep = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 21, 8)
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp_deep), 4, FAKE, FAKE, None,
+                               None) == spk.E_INVAL
+    tp_kd = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 2)
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp_kd), 4, FAKE, FAKE, None,
+                               None) == spk.E_UNSUPPORTED
+    bad = spk.opts("truncate", 2)
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(bad), ctypes.byref(tp), 4, FAKE, FAKE, None,
+                               None) == spk.E_UNSUPPORTED   # k below 3

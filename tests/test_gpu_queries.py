@@ -200,3 +200,109 @@ def test_rays_edge_cases(ctx):
         assert np.isfinite(th[i]) == np.isfinite(to[i])
     th2, it2 = _gpu_rays(ctx, net, o[1:2], d[1:2], delta=1e-3, max_iters=3)
     assert it2[0] <= 3
+
+
+def _l1_ball_distance(x, R):
+    """Euclidean distance from x outside/inside to the surface |y|_1 = R."""
+    ax = np.abs(np.asarray(x, dtype=np.float64))
+    s = ax.sum()
+    if s <= R:   # inside: the nearest face plane
+        return (R - s) / math.sqrt(3.0)
+    # outside: project |x| onto the simplex {y >= 0, sum y = R}
+    u = np.sort(ax)[::-1]
+    cs = np.cumsum(u)
+    rho = max(j for j in range(1, 4) if u[j - 1] - (cs[j - 1] - R) / j > 0)
+    theta = (cs[rho - 1] - R) / rho
+    return float(np.linalg.norm(ax - np.maximum(ax - theta, 0.0)))
+
+
+def _gpu_closest(ctx, net, q, max_level, policy="fixed", k=31):
+    import torch
+    from paper_2202_02444_amd import spk
+    g = spk.Net.from_spec(net)
+    dev = torch.device("cuda")
+    n = q.shape[0]
+    tq = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float32)).to(dev)
+    pt = torch.empty((n, 3), device=dev)
+    dist = torch.empty(n, device=dev)
+    bound = torch.empty(n, device=dev)
+    spk.closest_point(ctx, g, tq, pt, dist, bound, max_level=max_level, policy=policy, k=k)
+    ctx.sync()
+    return pt.cpu().numpy().astype(np.float64), dist.cpu().numpy().astype(np.float64), \
+        bound.cpu().numpy().astype(np.float64)
+
+
+def _spanning_cell_of(net, point, qpt, bound, max_level):
+    """Whether `point` is the center of a cell (some level <= max_level) of
+    [-1,1]^3 whose six face centers show both signs of f (FP64) and whose
+    farthest distance from the query equals `bound` (FP32 tolerance)."""
+    for level in range(max_level + 1):
+        size = 2.0 / (1 << level)
+        idx = (point + 1.0) / size - 0.5
+        if np.max(np.abs(idx - np.round(idx))) > 1e-4:
+            continue
+        lo = -1.0 + np.round(idx) * size
+        hi = lo + size
+        fv = omlp.forward(net, oq.face_centers(lo, hi))
+        md = float(np.linalg.norm(np.maximum(np.abs(qpt - lo), np.abs(qpt - hi))))
+        if np.any(fv < 0) and np.any(fv > 0) and abs(md - bound) <= 1e-5 * max(1.0, md):
+            return True
+    return False
+
+
+def test_closest_point_octahedron_closed_form(ctx):
+    """f = |x|_1 - R: the returned bound is at least the true distance, the
+    point lies within one cell of the surface, and the oracle agrees."""
+    R = 0.55
+    net = wl.octahedron_mlp(R, pad_to=32)
+    L = 6
+    diag = math.sqrt(3.0) * 2.0 / (1 << L)
+    q = wl.points(256, 40).astype(np.float64)
+    pt, dist, bound = _gpu_closest(ctx, net, q, L)
+    for i in range(q.shape[0]):
+        dstar = _l1_ball_distance(q[i], R)
+        assert np.all(np.isfinite(pt[i]))
+        assert bound[i] >= dstar - 1e-5
+        assert dstar - diag / 2 - 1e-5 <= dist[i] <= dstar + diag + 1e-5
+        assert abs(np.abs(pt[i]).sum() - R) <= math.sqrt(3.0) * diag / 2 + 1e-5
+        assert abs(dist[i] - np.linalg.norm(pt[i] - q[i])) <= 1e-5
+    for i in range(12):
+        _, d_o, b_o = oq.closest_point(net, q[i], max_level=L, policy="fixed")
+        assert abs(bound[i] - b_o) <= 1e-5 * max(1.0, b_o), (i, bound[i], b_o)
+
+
+@pytest.mark.parametrize("policy,k", [("fixed", 0), ("truncate", 16)])
+def test_closest_point_vs_oracle_tiny(ctx, policy, k):
+    """The tiny random net: the distance bound equals the oracle's best-first
+    search (up to cells whose classification or face-center signs sit at
+    rounding level), and every GPU answer is a spanning cell attaining it."""
+    net = wl.tiny_net(0)
+    L = 5
+    q = wl.points(24, 41).astype(np.float64)
+    pt, dist, bound = _gpu_closest(ctx, net, q, L, policy, k)
+    agree = 0
+    for i in range(q.shape[0]):
+        _, d_o, b_o = oq.closest_point(net, q[i], max_level=L, policy=policy, k=k)
+        if np.isfinite(b_o) and abs(bound[i] - b_o) <= 1e-5 * max(1.0, b_o):
+            agree += 1
+        if np.isfinite(bound[i]):
+            assert _spanning_cell_of(net, pt[i], q[i], bound[i], L), i
+            assert abs(dist[i] - np.linalg.norm(pt[i] - q[i])) <= 1e-5
+    assert agree >= q.shape[0] - 1
+
+
+def test_closest_point_edge_cases(ctx):
+    """No surface in the domain: NaN point, infinite distance and bound.
+    Queries outside the domain still find the surface inside it."""
+    net = wl.octahedron_mlp(0.55, pad_to=32)
+    far = wl.MLPSpec([np.zeros((32, 3), np.float32), np.zeros((1, 32), np.float32)],
+                     [np.zeros(32, np.float32), np.array([5.0], np.float32)], act="relu")
+    pt, dist, bound = _gpu_closest(ctx, far, wl.points(8, 42).astype(np.float64), 4)
+    assert np.all(np.isnan(pt)) and np.all(np.isinf(dist)) and np.all(np.isinf(bound))
+    q = np.array([[2.0, 2.0, 2.0], [-3.0, 0.1, 0.2], [0.0, 0.0, 0.0]])
+    pt, dist, bound = _gpu_closest(ctx, net, q, 5)
+    for i in range(3):
+        dstar = _l1_ball_distance(q[i], 0.55)
+        assert bound[i] >= dstar - 1e-5 and dist[i] <= dstar + math.sqrt(3.0) * 2.0 / 32 + 1e-5
+    pt1, _, b1 = _gpu_closest(ctx, net, q[:1], 5)
+    assert np.array_equal(b1, bound[:1])
