@@ -226,6 +226,58 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
                              const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,
                              float* bound);
 
+/*
+ * Batched bounds over many networks (Procedure 1 for each network's boxes).
+ * The batch groups its networks into classes (hidden width x activation),
+ * runs one persistent work-queue kernel per class and captures all of them
+ * once in a HIP graph: spk_batch_launch is a single graph launch that
+ * classifies every network's boxes, however uneven the box counts.
+ *
+ *   spk_batch_create  items host [n_items] (read during the call); the nets
+ *                     must live on the context's device and stay alive
+ *                     while the batch exists.  Writes descriptors to device
+ *                     memory it owns and captures the graph (synchronizes).
+ *   spk_batch_update  same networks in the same order with new box counts
+ *                     and buffers (e.g. the next frontier); no re-capture.
+ *   spk_batch_launch  enqueue the graph on the context's stream.
+ *   spk_batch_tune    autotuner: per class, times every launch shape
+ *                     (persistent workgroups 1, 2, 4 per CU x 1, 2, 8 groups
+ *                     per queue request) reps times on the current items,
+ *                     keeps the fastest and re-captures the graph.  Runs the
+ *                     class kernels, so the outputs are written.
+ *   spk_batch_classes the class table (n_classes set; up to cap entries).
+ */
+typedef struct {
+  const spk_net* net;
+  int64_t n;               /* boxes of this network (>= 0)                 */
+  const float* box_lo;     /* dev [n][3]                                    */
+  const float* box_hi;     /* dev [n][3]                                    */
+  uint8_t* label;          /* dev [n] uint8 class                           */
+  float* lo;               /* dev [n] nullable                              */
+  float* hi;               /* dev [n] nullable                              */
+} spk_batch_item;
+
+typedef struct spk_batch spk_batch;
+
+typedef struct {
+  int32_t width;           /* hidden width H                                */
+  int32_t act;             /* spk_act                                       */
+  int32_t term_slots;      /* 16 or 32 affine term slots per box            */
+  int32_t n_nets;
+  int64_t groups;          /* wavefront work items at the last update       */
+  int32_t blocks;          /* persistent workgroups of the class kernel     */
+  int32_t chunk;           /* groups per work-queue request                 */
+  float tuned_ms;          /* best time seen by spk_batch_tune (0: untuned)  */
+} spk_batch_class;
+
+spk_status spk_batch_create(spk_ctx* ctx, const spk_bound_opts* opts, int32_t n_items, const spk_batch_item* items,
+                            spk_batch** out);
+spk_status spk_batch_update(spk_ctx* ctx, spk_batch* batch, int32_t n_items, const spk_batch_item* items);
+spk_status spk_batch_launch(spk_ctx* ctx, spk_batch* batch);
+spk_status spk_batch_tune(spk_ctx* ctx, spk_batch* batch, int32_t reps);
+spk_status spk_batch_classes(const spk_batch* batch, int32_t* n_classes, spk_batch_class* out, int32_t cap);
+spk_status spk_batch_destroy(spk_batch* batch);
+
 /* Point evaluation f(x) for x dev [n][3] -> f dev [n] (FP32). */
 spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f);
 

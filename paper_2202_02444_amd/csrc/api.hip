@@ -38,15 +38,6 @@ bool finite_all(const float* p, size_t n) {
 
 spk_status check_hip(hipError_t e) { return e == hipSuccess ? SPK_OK : SPK_E_DEVICE; }
 
-spk_status valid_opts(const spk_bound_opts* o) {
-  if (o == nullptr) return SPK_E_INVAL;
-  if (o->prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;
-  if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
-  if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
-  if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;
-  if (o->flags & ~(uint32_t)SPK_FLAG_RIGOROUS) return SPK_E_INVAL;
-  return SPK_OK;
-}
 
 }  // namespace
 

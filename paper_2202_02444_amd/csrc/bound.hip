@@ -14,92 +14,16 @@
 // The center runs in FP64 because it carries the cancellation of every
 // layer: in FP32 its rounding grows to ~1e-4 of the bound on 8-layer
 // networks, while the generators and the condensed term stay accurate.
-#include "affine_stack.h"
+#include "bound_group.h"
 
 namespace spk {
-
-// Box of the bound job as an affine input: FP64 center, FP32 axes and the
-// input error radius that covers the rounding of the axes.
-__device__ __forceinline__ void box_input(const BoundJob& job, int64_t box, bool valid, double (&cc)[3],
-                                          float (&ax)[3][3], float (&ein)[3]) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    cc[d] = 0.0;
-    ein[d] = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) ax[q][d] = 0.0f;
-  }
-  if (!valid) return;
-  if (job.mode == IN_GENERAL) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) cc[d] = (double)job.a[3 * box + d];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) ax[q][d] = (q < job.s) ? job.b[(box * job.s + q) * 3 + d] : 0.0f;
-    return;
-  }
-  float lo[3], hi[3];
-  if (job.mode == IN_AABB) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { lo[d] = job.a[3 * box + d]; hi[d] = job.b[3 * box + d]; }
-  } else {
-    cell_box(job.cells[box], job.level, job.dom_lo, job.dom_hi, lo, hi);
-  }
-  // center and half-width of the FP32 box, exactly, in FP64 (Procedure 3:
-  // x_c = (x_l + x_u)/2, v = x_u - x_c); the half-width is then rounded to
-  // FP32 for the generator, its rounding kept in ein
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    cc[d] = 0.5 * ((double)lo[d] + (double)hi[d]);
-    const double h = (double)hi[d] - cc[d];
-    ax[d][d] = (float)h;
-    ein[d] = 2.0f * kU * fabsf((float)h) + kEta;
-  }
-}
 
 template <class S, int ACT, int POL>
 __global__ __launch_bounds__(64, 1) void bound_kernel(NetDev net, BoundJob job) {
   __shared__ __attribute__((aligned(16))) LdsState<S> sm;
-  constexpr int NS = S::NS, BPW = S::BPW, SEG = S::SEG;
-  const int lane = threadIdx.x;
-  const int bo = lane / SEG;
-  const int ch = lane % SEG;
-  const int64_t ngroups = (job.n + BPW - 1) / BPW;
-  const int L = net.L;
-
-  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    const int64_t box = grp * BPW + bo;
-    const bool valid = box < job.n;
-    double cc[3];
-    float ax[3][3], ein[3], pts[1][3] = {{0.0f, 0.0f, 0.0f}};
-    box_input(job, box, valid, cc, ax, ein);
-    double xc[4];
-    f4 y[NS];
-    float yinf[4], e[4], u[4];
-    layer0_affine<S, 0>(net, ch, cc, ax, ein, pts, xc, y, yinf, e);
-    int n_occ = job.s;
-    for (int a = 0; a < L - 1; ++a) {
-      int16_t* rec = nullptr;
-      if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
-      n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, net.cK, net.cD, net.omega0, lane, rec);
-      if (a == L - 2) break;
-      hidden_layer<S, 0>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
-    }
-    float pass[1];
-    const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass);
-    if (valid && ch == 0) {
-      float lo, hi;
-      enclose(o, job.rigorous != 0, lo, hi);
-      if (job.lo) job.lo[box] = lo;
-      if (job.hi) job.hi[box] = hi;
-      if (job.label) job.label[box] = (lo > 0.0f) ? (uint8_t)SPK_POSITIVE
-                                      : (hi < 0.0f) ? (uint8_t)SPK_NEGATIVE : (uint8_t)SPK_UNKNOWN;
-      if (job.center) job.center[box] = (float)o.y0;
-      if (job.radius) job.radius[box] = o.r;
-      if (job.err) job.err[box] = job.rigorous ? o.err : round_up_f(tolerance_margin(o));
-    }
-  }
+  const int64_t ngroups = (job.n + S::BPW - 1) / S::BPW;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x)
+    bound_group<S, ACT, POL>(net, job, sm, grp, (int)threadIdx.x);
 }
 
 template <class S, int ACT, int POL>

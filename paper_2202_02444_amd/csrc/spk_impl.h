@@ -121,6 +121,17 @@ struct spk_ctx {
 };
 
 namespace spk {
+// Validation of the bound options shared by every entry point.
+inline spk_status valid_opts(const spk_bound_opts* o) {
+  if (o == nullptr) return SPK_E_INVAL;
+  if (o->prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;
+  if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
+  if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
+  if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;
+  if (o->flags & ~(uint32_t)SPK_FLAG_RIGOROUS) return SPK_E_INVAL;
+  return SPK_OK;
+}
+
 // Launch helpers implemented in bound.hip / tree.hip / rays.hip.
 spk_status launch_bound(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus);
 spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t n, bool at_max,

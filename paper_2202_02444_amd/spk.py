@@ -22,7 +22,21 @@ UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
-           "spk_subdivide_frontier", "spk_cast_rays", "spk_eval_points", "spk_closest_point")
+           "spk_subdivide_frontier", "spk_cast_rays", "spk_eval_points", "spk_closest_point",
+           "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
+           "spk_batch_destroy")
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("net", ctypes.c_void_p), ("n", ctypes.c_int64), ("box_lo", ctypes.c_void_p),
+                ("box_hi", ctypes.c_void_p), ("label", ctypes.c_void_p), ("lo", ctypes.c_void_p),
+                ("hi", ctypes.c_void_p)]
+
+
+class BatchClass(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("act", ctypes.c_int32), ("term_slots", ctypes.c_int32),
+                ("n_nets", ctypes.c_int32), ("groups", ctypes.c_int64), ("blocks", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("tuned_ms", ctypes.c_float)]
 
 
 class BoundOpts(ctypes.Structure):
@@ -75,6 +89,13 @@ def lib():
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
         L.spk_eval_points.argtypes = [vp, vp, i64, vp, vp]
+        L.spk_batch_create.argtypes = [vp, ctypes.POINTER(BoundOpts), i32, ctypes.POINTER(BatchItem),
+                                       ctypes.POINTER(vp)]
+        L.spk_batch_update.argtypes = [vp, vp, i32, ctypes.POINTER(BatchItem)]
+        L.spk_batch_launch.argtypes = [vp, vp]
+        L.spk_batch_tune.argtypes = [vp, vp, i32]
+        L.spk_batch_classes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(BatchClass), i32]
+        L.spk_batch_destroy.argtypes = [vp]
         L.spk_closest_point.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i64, vp, vp,
                                         vp, vp]
         for name in EXPORTS:
@@ -260,6 +281,66 @@ def closest_point(ctx, net, q, point, dist=None, bound=None, max_level=8, policy
                                  _ptr(q, torch.float32, (n, 3), "q"), _ptr(point, torch.float32, (n, 3), "point"),
                                  _ptr(dist, torch.float32, (n,), "dist"), _ptr(bound, torch.float32, (n,), "bound"))
     _check(st, "spk_closest_point")
+
+
+class Batch:
+    """spk_batch_*: one graph launch bounding the boxes of many networks.
+
+    items: list of dicts with keys net (Net), box_lo, box_hi ([n, 3] float32
+    device tensors), label ([n] uint8) and optionally lo, hi ([n] float32)."""
+
+    def __init__(self, ctx, items, policy="truncate", k=31, rigorous=False):
+        self.handle = None
+        self._keep = None
+        arr = self._items(items)
+        o = opts(policy, k, rigorous)
+        h = ctypes.c_void_p()
+        _check(lib().spk_batch_create(ctx.handle, ctypes.byref(o), len(items), arr, ctypes.byref(h)),
+               "spk_batch_create")
+        self.handle = h
+
+    def _items(self, items):
+        import torch
+        arr = (BatchItem * len(items))()
+        for i, it in enumerate(items):
+            n = it["box_lo"].shape[0]
+            def v(p):
+                return None if p is None else p.value
+            arr[i] = BatchItem(it["net"].handle.value, n, v(_ptr(it["box_lo"], torch.float32, (n, 3), "box_lo")),
+                               v(_ptr(it["box_hi"], torch.float32, (n, 3), "box_hi")),
+                               v(_ptr(it["label"], torch.uint8, (n,), "label")),
+                               v(_ptr(it.get("lo"), torch.float32, (n,), "lo")),
+                               v(_ptr(it.get("hi"), torch.float32, (n,), "hi")))
+        self._keep = list(items)   # the device buffers must outlive their use
+        return arr
+
+    def update(self, ctx, items):
+        arr = self._items(items)
+        _check(lib().spk_batch_update(ctx.handle, self.handle, len(items), arr), "spk_batch_update")
+
+    def launch(self, ctx):
+        _check(lib().spk_batch_launch(ctx.handle, self.handle), "spk_batch_launch")
+
+    def tune(self, ctx, reps=3):
+        _check(lib().spk_batch_tune(ctx.handle, self.handle, int(reps)), "spk_batch_tune")
+
+    def classes(self):
+        n = ctypes.c_int32()
+        _check(lib().spk_batch_classes(self.handle, ctypes.byref(n), None, 0), "spk_batch_classes")
+        out = (BatchClass * max(n.value, 1))()
+        _check(lib().spk_batch_classes(self.handle, ctypes.byref(n), out, n.value), "spk_batch_classes")
+        return [{f: getattr(out[i], f) for f, _ in BatchClass._fields_} for i in range(n.value)]
+
+    def close(self):
+        if self.handle:
+            _check(lib().spk_batch_destroy(self.handle), "spk_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def eval_points(ctx, net, x, f):

@@ -125,3 +125,21 @@ def test_closest_point_validation():
     bad = spk.opts("truncate", 2)
     assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(bad), ctypes.byref(tp), 4, FAKE, FAKE, None,
                                None) == spk.E_UNSUPPORTED   # k below 3
+
+
+def test_batch_validation():
+    L = spk.lib()
+    o = spk.opts("truncate", 31)
+    h = ctypes.c_void_p()
+    items = (spk.BatchItem * 1)()
+    items[0] = spk.BatchItem(None, 4, 0x1000, 0x1000, 0x1000, None, None)
+    assert L.spk_batch_create(FAKE, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_INVAL   # null net
+    assert L.spk_batch_create(FAKE, ctypes.byref(o), 0, items, ctypes.byref(h)) == spk.E_INVAL   # no items
+    assert L.spk_batch_create(None, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_INVAL
+    bad = spk.opts("truncate", 40)
+    assert L.spk_batch_create(FAKE, ctypes.byref(bad), 1, items, ctypes.byref(h)) == spk.E_UNSUPPORTED
+    assert L.spk_batch_launch(FAKE, None) == spk.E_INVAL
+    assert L.spk_batch_tune(FAKE, None, 3) == spk.E_INVAL
+    assert L.spk_batch_destroy(None) == spk.E_INVAL
+    n = ctypes.c_int32()
+    assert L.spk_batch_classes(None, ctypes.byref(n), None, 0) == spk.E_INVAL

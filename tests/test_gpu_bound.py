@@ -229,3 +229,28 @@ def test_rigorous_mode_every_kernel(ctx, act, H):
             lo_o, hi_o = omlp.bound_boxes(net, lo, hi, policy, k)[2:]
         S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
         assert endpoint_errors(out["center"], out["radius"], lo_o, hi_o, S).max() <= TOL, (policy, k)
+
+
+@pytest.mark.parametrize("act", ["relu", "elu", "sin"])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_every_kernel_deterministic_and_in_parity(ctx, act, depth):
+    """Every kernel instantiation (width x term slots x policy) at 1-3 hidden
+    layers, on enough boxes to fill many workgroups: two launches agree bit
+    for bit and the raw bound matches the oracle (truncation replayed)."""
+    from paper_2202_02444_amd import spk
+    lo, hi = wl.boxes(1500, 65, 1e-3, 0.25)
+    for H in (32, 64, 128, 256):
+        widths = [3] + [H] * depth + [1]
+        net = wl.siren_mlp(widths, 54, 30.0) if act == "sin" else wl.he_normal_mlp(widths, 54, act=act)
+        g = spk.Net.from_spec(net)
+        for policy, k in (("truncate", 31), ("truncate", 15), ("fixed", 0)):
+            o1 = gpu_classify(ctx, g, lo, hi, policy, k, want_src=(policy == "truncate"))
+            o2 = gpu_classify(ctx, g, lo, hi, policy, k)
+            assert np.array_equal(o1["lo"], o2["lo"]) and np.array_equal(o1["hi"], o2["hi"]), (H, policy, k)
+            if policy == "truncate":
+                sets = keep_sets_from_src(o1["src"], 3, k, H)
+                lo_o, hi_o = omlp.bound_boxes(net, lo, hi, policy, k, keep_sets=sets)[2:]
+            else:
+                lo_o, hi_o = omlp.bound_boxes(net, lo, hi, policy, k)[2:]
+            S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+            assert endpoint_errors(o1["center"], o1["radius"], lo_o, hi_o, S).max() <= TOL, (H, policy, k)
