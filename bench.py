@@ -35,6 +35,88 @@ def algorithmic_flops_per_box(H=256, n_hidden_layers=7, k=K_KEEP):
     return n_hidden_layers * (2.0 * H * H * (1 + k) + 2.0 * H * H)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "bound_kernel_blob8x256_1M_truncate31.md")
+KERNEL_SOURCES = ["paper_2202_02444_amd/csrc/affine_core.h", "paper_2202_02444_amd/csrc/affine_stack.h",
+                  "paper_2202_02444_amd/csrc/bound_group.h", "paper_2202_02444_amd/csrc/bound.hip",
+                  "paper_2202_02444_amd/csrc/spk_impl.h", "paper_2202_02444_amd/build.py"]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter profile, or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        fields = dict(line.split(": ", 1) for line in text.splitlines()
+                      if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
+        if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def closest_point_extra(ctx, dev, n=4096, max_level=10):
+    """Closest point (Section 4.10) for n uniform queries, affine-fixed cells,
+    on the tiny 3->32->32->1 ReLU net.  (On the 8x256 blob the affine-fixed
+    bounds leave nearly every cell above level 8 UNKNOWN, so the exact search
+    visits a large part of the tree per query.)"""
+    import torch
+    import workloads as wl
+    from paper_2202_02444_amd import spk
+    g = spk.Net.from_spec(wl.tiny_net(0))
+    q = torch.from_numpy(wl.points(n, 501)).to(dev)
+    pt = torch.empty((n, 3), device=dev)
+    dist = torch.empty(n, device=dev)
+    t = time.perf_counter()
+    spk.closest_point(ctx, g, q, pt, dist, max_level=max_level, policy="fixed")
+    dt = time.perf_counter() - t
+    return {"net": "3->32->32->1 ReLU (tiny)", "queries": n, "max_level": max_level, "queries_per_s": n / dt,
+            "found": int(torch.isfinite(dist).sum().item())}
+
+
+def batched_extra(ctx, dev, policy="truncate", k=K_KEEP):
+    """64 networks (widths 64/128/256, depths 4-8, ReLU/ELU/sine) with uneven
+    box frontiers (1e3-2e5 boxes each): one tuned graph launch against one
+    classify launch per network."""
+    import torch
+    import workloads as wl
+    from paper_2202_02444_amd import spk
+    nets = wl.batched_nets()
+    sizes = wl.batched_frontier_sizes()
+    items = []
+    for i, (net, n) in enumerate(zip(nets, sizes)):
+        lo, hi = wl.boxes(n, 200 + i, 1e-4, 0.5)
+        items.append({"net": spk.Net.from_spec(net), "box_lo": torch.from_numpy(lo).to(dev),
+                      "box_hi": torch.from_numpy(hi).to(dev),
+                      "label": torch.empty(n, dtype=torch.uint8, device=dev)})
+    total = int(sum(sizes))
+    b = spk.Batch(ctx, items, policy, k)
+    b.tune(ctx, reps=1)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    b.launch(ctx)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    b.launch(ctx)
+    ev[1].record(stream)
+    for it in items:
+        spk.classify_boxes(ctx, it["net"], it["box_lo"], it["box_hi"], it["label"], None, None, policy, k)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    graph_ms = ev[0].elapsed_time(ev[1])
+    seq_ms = ev[1].elapsed_time(ev[2])
+    classes = b.classes()
+    b.close()
+    return {"nets": len(nets), "boxes": total, "graph_boxes_per_s": total / (graph_ms * 1e-3),
+            "sequential_boxes_per_s": total / (seq_ms * 1e-3), "graph_ms": graph_ms, "sequential_ms": seq_ms,
+            "classes": [{"width": c["width"], "act": c["act"], "nets": c["n_nets"], "blocks": c["blocks"],
+                         "chunk": c["chunk"]} for c in classes]}
+
+
 def cpu_baseline(net, lo, hi, n_sample):
     """The FP64 oracle, as it stands, on a bounded sample of the same boxes."""
     from oracle import mlp as omlp
@@ -49,6 +131,11 @@ def cpu_baseline(net, lo, hi, n_sample):
     return {"value": n_sample / dt, "unit": "boxes/s", "cores": int(cores), "kind": "oracle",
             "sample": "%d of the %d boxes (FP64 NumPy oracle, affine-truncate k=%d), %.1f s" % (
                 n_sample, N_BOXES, K_KEEP, dt)}
+
+
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def main():
@@ -92,6 +179,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    progress("warmup done")
     stream = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -107,6 +195,7 @@ def main():
     value = args.boxes * args.steps / wall
     fl = algorithmic_flops_per_box() * args.boxes
     achieved = fl / (np.mean(kern_ms) * 1e-3)
+    progress("timed steps done: %.1f ms per step" % ms_per_step)
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
@@ -126,7 +215,8 @@ def main():
                    "boxes": args.boxes, "k": K_KEEP, "hidden": "256x8", "policy": "truncate",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": measured_traffic() if args.boxes == N_BOXES else None,
                      "kernel_ms": float(np.mean(kern_ms)),
                      "flop_per_box": algorithmic_flops_per_box()},
         "labels": {"pos": int((labels == 1).sum()), "neg": int((labels == 2).sum()),
@@ -140,6 +230,7 @@ def main():
         extra["octree_depth10_s"] = time.perf_counter() - t
         extra["octree_leaves"] = int(leaves.shape[0])
         extra["octree_frontier"] = [lv["n"] for lv in levels]
+        progress("octree done")
         try:
             o, d = wl.camera_rays(512, 512, 600)
             to = torch.from_numpy(o).to(dev)
@@ -153,12 +244,18 @@ def main():
             dt = time.perf_counter() - t
             extra["rays_per_s"] = o.shape[0] / dt
             extra["ray_hits"] = int(torch.isfinite(th).sum().item())
+            progress("rays done")
         except spk.SpkError as exc:
             extra["rays_per_s"] = None
             extra["rays_note"] = str(exc)
+        extra["closest_point"] = closest_point_extra(ctx, dev)
+        progress("closest point done")
+        extra["batched"] = batched_extra(ctx, dev)
+        progress("batched done")
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, lo, hi, args.cpu_sample)
+        progress("cpu baseline done")
     print(json.dumps(out))
 
 

@@ -242,9 +242,11 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
  *   spk_batch_launch  enqueue the graph on the context's stream.
  *   spk_batch_tune    autotuner: per class, times every launch shape
  *                     (persistent workgroups 1, 2, 4 per CU x 1, 2, 8 groups
- *                     per queue request) reps times on the current items,
- *                     keeps the fastest and re-captures the graph.  Runs the
- *                     class kernels, so the outputs are written.
+ *                     per queue request) reps times on the current items and
+ *                     keeps the fastest; then times the whole graph with the
+ *                     class kernels as parallel branches and as a chain, and
+ *                     keeps the faster capture.  Runs the kernels, so the
+ *                     outputs are written.
  *   spk_batch_classes the class table (n_classes set; up to cap entries).
  */
 typedef struct {

@@ -354,6 +354,8 @@ struct CallBuffers {
     if (bytes <= cap) return SPK_OK;
     const size_t want = bytes + bytes / 2;
     if (limit && total - cap + want > limit) return SPK_E_NOMEM;
+    // earlier launches of the call may still read the old buffer
+    if (*p && hipStreamSynchronize(stream) != hipSuccess) return SPK_E_DEVICE;
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     total -= cap;
@@ -369,28 +371,39 @@ struct CallBuffers {
 };
 }  // namespace
 
-spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
-                             const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,
-                             float* bound) {
-  if (ctx == nullptr || net == nullptr || tree == nullptr) return SPK_E_INVAL;
-  spk_status st = valid_opts(opts);
-  if (st != SPK_OK) return st;
-  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
-  if (tree->max_level < 0 || tree->max_level > 20) return SPK_E_INVAL;
-  for (int d = 0; d < 3; ++d)
-    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
-      return SPK_E_INVAL;
-  if (n < 0 || n > (int64_t)0xffffffffLL) return SPK_E_INVAL;
-  if (n == 0) return SPK_OK;
-  if (q == nullptr || point == nullptr) return SPK_E_INVAL;
-
+// One chunk of queries through every level (see spk_closest_point); the
+// buffers are reused from chunk to chunk.
+struct CpBuffers {
   CallBuffers B;
-  B.limit = ctx->workspace_limit;
-  B.stream = ctx->stream;
   void *best = nullptr, *codes = nullptr, *qidx = nullptr, *ncodes = nullptr, *nqidx = nullptr, *labels = nullptr,
        *fpts = nullptr, *fvals = nullptr, *cnt = nullptr;
   size_t c_best = 0, c_codes = 0, c_qidx = 0, c_ncodes = 0, c_nqidx = 0, c_labels = 0, c_fpts = 0, c_fvals = 0,
          c_cnt = 0;
+};
+
+static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                                const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,
+                                float* bound, CpBuffers& CB) {
+  CallBuffers& B = CB.B;
+  void*& best = CB.best;
+  void*& codes = CB.codes;
+  void*& qidx = CB.qidx;
+  void*& ncodes = CB.ncodes;
+  void*& nqidx = CB.nqidx;
+  void*& labels = CB.labels;
+  void*& fpts = CB.fpts;
+  void*& fvals = CB.fvals;
+  void*& cnt = CB.cnt;
+  size_t& c_best = CB.c_best;
+  size_t& c_codes = CB.c_codes;
+  size_t& c_qidx = CB.c_qidx;
+  size_t& c_ncodes = CB.c_ncodes;
+  size_t& c_nqidx = CB.c_nqidx;
+  size_t& c_labels = CB.c_labels;
+  size_t& c_fpts = CB.c_fpts;
+  size_t& c_fvals = CB.c_fvals;
+  size_t& c_cnt = CB.c_cnt;
+  spk_status st = SPK_OK;
 #define SPK_ENSURE(ptr, cap, bytes)                 \
   do {                                              \
     spk_status e_ = B.ensure(&(ptr), cap, (bytes)); \
@@ -462,8 +475,36 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
     std::swap(c_qidx, c_nqidx);
   }
 #undef SPK_ENSURE
-  st = launch_cp_finish(n, q, (const unsigned*)best, point, dist, bound, ctx->stream, ctx->num_cus);
+  return launch_cp_finish(n, q, (const unsigned*)best, point, dist, bound, ctx->stream, ctx->num_cus);
+}
+
+
+spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                             const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,
+                             float* bound) {
+  if (ctx == nullptr || net == nullptr || tree == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
   if (st != SPK_OK) return st;
+  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
+  if (tree->max_level < 0 || tree->max_level > 20) return SPK_E_INVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
+      return SPK_E_INVAL;
+  if (n < 0 || n > (int64_t)0xffffffffLL) return SPK_E_INVAL;
+  if (n == 0) return SPK_OK;
+  if (q == nullptr || point == nullptr) return SPK_E_INVAL;
+
+  // queries run in chunks so that the frontier memory stays bounded
+  constexpr int64_t kChunk = 1024;
+  CpBuffers CB;
+  CB.B.limit = ctx->workspace_limit;
+  CB.B.stream = ctx->stream;
+  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+    const int64_t cn = (n - c0 < kChunk) ? n - c0 : kChunk;
+    st = closest_chunk(ctx, net, opts, tree, cn, q + 3 * c0, point + 3 * c0, dist ? dist + c0 : nullptr,
+                       bound ? bound + c0 : nullptr, CB);
+    if (st != SPK_OK) return st;
+  }
   return check_hip(hipStreamSynchronize(ctx->stream));
 }
 

@@ -131,6 +131,8 @@ struct spk_batch {
   hipGraphExec_t exec = nullptr;
   std::vector<hipStream_t> side;   // capture-time fork streams
   std::vector<hipEvent_t> ev;
+  bool concurrent = true;          // class kernels as parallel graph branches
+  float graph_ms = 0.0f;           // tuned time of one graph launch
 };
 
 namespace {
@@ -196,8 +198,9 @@ void drop_graph(spk_batch* b) {
   b->graph = nullptr;
 }
 
-// Capture: zero the counters, then fork one branch per class (independent
-// graph nodes that the runtime may run side by side) and join.
+// Capture: zero the counters, then either fork one branch per class
+// (independent graph nodes that the runtime may run side by side) and join,
+// or chain the class kernels one after another.
 spk_status capture(spk_batch* b) {
   drop_graph(b);
   const int nc = (int)b->classes.size();
@@ -220,8 +223,12 @@ spk_status capture(spk_batch* b) {
     hipLaunchKernelGGL(spk::batch_zero_kernel, dim3(1), dim3(64), 0, cs, counters, nc, kCounterStride);
     bool ok = hipGetLastError() == hipSuccess && hipEventRecord(b->ev[nc], cs) == hipSuccess;
     for (int c = 0; ok && c < nc; ++c) {
-      ok = hipStreamWaitEvent(b->side[c], b->ev[nc], 0) == hipSuccess;
       const ClassPlan& p = b->classes[c];
+      if (!b->concurrent) {
+        ok = spk::launch_class(p.H, p.act, p.nt, b->opts.policy, class_args(b, c), p.blocks, cs) == hipSuccess;
+        continue;
+      }
+      ok = hipStreamWaitEvent(b->side[c], b->ev[nc], 0) == hipSuccess;
       if (ok) ok = spk::launch_class(p.H, p.act, p.nt, b->opts.policy, class_args(b, c), p.blocks, b->side[c]) ==
                    hipSuccess;
       if (ok) ok = hipEventRecord(b->ev[c], b->side[c]) == hipSuccess;
@@ -375,9 +382,36 @@ spk_status spk_batch_tune(spk_ctx* ctx, spk_batch* b, int32_t reps) {
     p.chunk = best_chunk;
     p.tuned_ms = best > 0.0f ? best : 0.0f;
   }
+  // whole graph: parallel class branches or a chain, whichever is faster
+  float best_graph = -1.0f;
+  bool best_conc = true;
+  for (int conc = 1; conc >= 0 && st == SPK_OK; --conc) {
+    b->concurrent = conc != 0;
+    st = capture(b);
+    float total = 0.0f;
+    for (int r = 0; r <= reps && st == SPK_OK; ++r) {
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess || hipGraphLaunch(b->exec, ctx->stream) != hipSuccess ||
+          hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = SPK_E_DEVICE;
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) total += ms;
+    }
+    const float avg = total / (float)reps;
+    if (st == SPK_OK && (best_graph < 0.0f || avg < best_graph)) {
+      best_graph = avg;
+      best_conc = conc != 0;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st == SPK_OK) st = capture(b);
+  if (st == SPK_OK) {
+    b->concurrent = best_conc;
+    b->graph_ms = best_graph;
+    st = capture(b);
+  }
   return st;
 }
 
