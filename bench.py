@@ -117,6 +117,55 @@ def batched_extra(ctx, dev, policy="truncate", k=K_KEEP):
                          "chunk": c["chunk"]} for c in classes]}
 
 
+def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, n_sample=2048, steps=2):
+    """Split-BF16 generator products (SPK_PREC_BF16X3) against FP32, both with
+    the rigorous rounding radius: boxes/s on the full batch, and on a sample
+    the bound width relative to the FP64 oracle's exact affine bound (same
+    kept terms), label agreement and sampled soundness."""
+    import torch
+    from oracle import mlp as omlp
+    from paper_2202_02444_amd import spk
+    n = tlo.shape[0]
+    lab = torch.empty(n, dtype=torch.uint8, device=dev)
+    res = {}
+    stream = torch.cuda.current_stream()
+    for prec in ("f32", "bf16x3"):
+        spk.classify_boxes(ctx, g, tlo, thi, lab, None, None, "truncate", K_KEEP, rigorous=True, prec=prec)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            spk.classify_boxes(ctx, g, tlo, thi, lab, None, None, "truncate", K_KEEP, rigorous=True, prec=prec)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        # sample: bounds, kept terms, oracle replay
+        m = n_sample
+        slo, shi = tlo[:m].contiguous(), thi[:m].contiguous()
+        glo = torch.empty(m, device=dev)
+        ghi = torch.empty(m, device=dev)
+        gl = torch.empty(m, dtype=torch.uint8, device=dev)
+        src = torch.full((len(net.weights) - 1, m, 32), -3, dtype=torch.int16, device=dev)
+        spk.classify_boxes(ctx, g, slo, shi, gl, glo, ghi, "truncate", K_KEEP, aux={"slot_src": src},
+                           rigorous=True, prec=prec)
+        torch.cuda.synchronize()
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import keep_sets_from_src, soundness_violations
+        sets = keep_sets_from_src(src.cpu().numpy(), 3, K_KEEP, 256)
+        lo_o, hi_o = omlp.bound_boxes(net, lo[:m], hi[:m], "truncate", K_KEEP, keep_sets=sets)[2:]
+        glo_n = glo.cpu().numpy().astype(np.float64)
+        ghi_n = ghi.cpu().numpy().astype(np.float64)
+        ratio = (ghi_n - glo_n) / np.maximum(hi_o - lo_o, 1e-300)
+        lab_o = np.where(lo_o > 0, 1, np.where(hi_o < 0, 2, 0))
+        bad, f = soundness_violations(net, lo[:m], hi[:m], glo_n, ghi_n, np.random.default_rng(7))
+        res[prec] = {"boxes_per_s": n / (ms * 1e-3), "ms_per_launch": ms,
+                     "width_ratio_median": float(np.median(ratio)), "width_ratio_p99": float(np.percentile(ratio, 99)),
+                     "contains_oracle": bool(np.all(glo_n <= lo_o) and np.all(ghi_n >= hi_o)),
+                     "label_agreement": float(np.mean(gl.cpu().numpy() == lab_o)),
+                     "sampled_points": int(f.size), "soundness_violations": bad}
+    res["sample_boxes"] = n_sample
+    return res
+
+
 def cpu_baseline(net, lo, hi, n_sample):
     """The FP64 oracle, as it stands, on a bounded sample of the same boxes."""
     from oracle import mlp as omlp
@@ -252,6 +301,8 @@ def main():
         progress("closest point done")
         extra["batched"] = batched_extra(ctx, dev)
         progress("batched done")
+        extra["precision"] = precision_extra(ctx, g, net, tlo, thi, lo, hi, dev)
+        progress("precision done")
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, lo, hi, args.cpu_sample)

@@ -59,8 +59,16 @@ typedef enum { SPK_ACT_RELU = 0, SPK_ACT_ELU = 1, SPK_ACT_SIN = 2 } spk_act;
  * GPU (SPK_E_UNSUPPORTED). */
 typedef enum { SPK_AFFINE_FIXED = 0, SPK_AFFINE_TRUNCATE = 1, SPK_AFFINE_FULL = 2 } spk_policy;
 
-/* Arithmetic of the generator products. */
-typedef enum { SPK_PREC_F32 = 0 } spk_prec;
+/* Arithmetic of the generator products Y = W X of the hidden layers.
+ *  SPK_PREC_F32    FP32 MFMA (16x16x4), FP32 accumulation.
+ *  SPK_PREC_BF16X3 split BF16: W = W_hi + W_lo and X = X_hi + X_lo (round to
+ *                  nearest BF16 each), W_hi X_hi + W_hi X_lo + W_lo X_hi on the
+ *                  BF16 MFMA (16x16x32) with FP32 accumulation.  The dropped
+ *                  W_lo X_lo and split residuals are bounded a priori and the
+ *                  rigorous rounding radius is always applied (as with
+ *                  SPK_FLAG_RIGOROUS).  Hidden width 256 only (else
+ *                  SPK_E_UNSUPPORTED); single-network bound calls only. */
+typedef enum { SPK_PREC_F32 = 0, SPK_PREC_BF16X3 = 1 } spk_prec;
 
 /* uint8 sign classes of Procedure 1. */
 enum { SPK_UNKNOWN = 0, SPK_POSITIVE = 1, SPK_NEGATIVE = 2 };

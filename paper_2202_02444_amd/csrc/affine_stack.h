@@ -347,6 +347,104 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
   __syncthreads();
 }
 
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+// Split 8 floats into BF16 hi and lo parts (round to nearest even each): the
+// residual v - hi is exact in FP32.
+__device__ __forceinline__ void split_bf16(const f4& a, const f4& b, bf8& hi, bf8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float v = i < 4 ? a[i] : b[i - 4];
+    const __bf16 h = (__bf16)v;
+    hi[i] = h;
+    lo[i] = (__bf16)(v - (float)h);
+  }
+}
+
+// Column tile n of the wave's single box (H = 256) with split-BF16 generator
+// products: W_hi X_hi + W_hi X_lo + W_lo X_hi on the 16x16x32 BF16 MFMA, K in
+// blocks of 32 rows (lane (g, c) holds rows 32 t2 + 8 g .. + 7 of column c).
+// The FP64 center and the |W| products run first on VALU over the FP32
+// fragments (first pass only).
+template <class S, int VA>
+__device__ __forceinline__ void single_box_pass_split(LdsState<S>& sm, const f4* Wl, const uint32_t* Wbl, int n,
+                                                      int lane) {
+  constexpr int MT = S::MT, MT2 = MT / 2, PF = 4;
+  static_assert(S::BPW == 1 && MT % PF == 0, "one box per wave; the ring index repeats every K block");
+  const int g = lane >> 4, c = lane & 15;
+  f4 acc[MT];
+  float px[MT], pe[MT];
+  double pd[MT];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+    px[tp] = 0.0f;
+    pe[tp] = 0.0f;
+    pd[tp] = 0.0;
+  }
+  if (VA != VA_NONE) {
+    const f4* Wq = Wl + lane;
+    f4 ring[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+#pragma unroll 1
+    for (int t = 0; t < MT; ++t) {
+      const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
+      f4 ve = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[16 * t + 4 * g];
+      double vd[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
+#pragma unroll
+      for (int tp = 0; tp < MT; ++tp) {
+        const f4 w = ring[tp % PF];
+        const int qn = min(t * MT + tp + PF, MT * MT - 1);
+        ring[tp % PF] = Wq[(size_t)qn * 64];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
+          pd[tp] = fma((double)w[j], vd[j], pd[tp]);
+          if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
+        }
+      }
+    }
+  }
+  // fragment (t2, tp): two 16-byte vectors (8 hi, 8 lo BF16) per lane
+  const u4v* Bq = (const u4v*)Wbl + 2 * lane;
+  u4v rh[PF], rl[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    rh[p] = Bq[(size_t)p * 128];
+    rl[p] = Bq[(size_t)p * 128 + 1];
+  }
+#pragma unroll 1
+  for (int t2 = 0; t2 < MT2; ++t2) {
+    const f4 b0 = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 8 * t2 + 2 * g)];
+    const f4 b1 = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 8 * t2 + 2 * g + 1)];
+    bf8 xh, xl;
+    split_bf16(b0, b1, xh, xl);
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      const bf8 ah = __builtin_bit_cast(bf8, rh[tp % PF]);
+      const bf8 al = __builtin_bit_cast(bf8, rl[tp % PF]);
+      const int qn = min(t2 * MT + tp + PF, MT2 * MT - 1);   // past the end: a harmless reload
+      rh[tp % PF] = Bq[(size_t)qn * 128];
+      rl[tp % PF] = Bq[(size_t)qn * 128 + 1];
+      acc[tp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh, acc[tp], 0, 0, 0);
+      acc[tp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xl, acc[tp], 0, 0, 0);
+      acc[tp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh, acc[tp], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    if (VA != VA_NONE) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+    *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = acc[tp];
+  }
+  __syncthreads();
+}
+
 // Column tile n of every box of the wave (H < 256: several boxes) through one
 // H -> H layer.  This K block's A fragments are held for every output tile
 // (MT is small here) and reused box after box.
@@ -421,7 +519,7 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
 // owner layout through the LDS tile.  Ends with the pre-activation form of
 // the next activation: centers with bias (FP64), generators, condensed term,
 // error radius; passengers receive the bias too.
-template <class S, int NPASS>
+template <class S, int NPASS, int PREC = SPK_PREC_F32>
 __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm, int a, double (&xc)[4],
                                              f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
                                              const float (&u)[4], int lane, bool rigorous) {
@@ -448,7 +546,16 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
 
   // ---- generators on MFMA, center in FP64, |W| xinf and |W| u on VALU ----
   const f4* Wl = (const f4*)net.Wp + (size_t)a * (H * H / 4);
-  if constexpr (BPW == 1) {
+  if constexpr (PREC == SPK_PREC_BF16X3) {
+    static_assert(BPW == 1, "split-BF16 products are built for one box per wave");
+    const uint32_t* Wbl = net.Wb + (size_t)a * (H * H);   // H*H (hi, lo) pairs of 16-bit values
+    if (rigorous)
+      single_box_pass_split<S, VA_RIGOROUS>(sm, Wl, Wbl, 0, lane);
+    else
+      single_box_pass_split<S, VA_CENTER>(sm, Wl, Wbl, 0, lane);
+#pragma unroll 1
+    for (int n = 1; n < NT; ++n) single_box_pass_split<S, VA_NONE>(sm, Wl, Wbl, n, lane);
+  } else if constexpr (BPW == 1) {
     if (rigorous)
       single_box_pass<S, VA_RIGOROUS>(sm, Wl, 0, lane);
     else

@@ -30,6 +30,32 @@ double dot_const(int n, int mantissa_bits) {
   return m * up / (1.0 - m * up) * (1.0 + 1e-6);
 }
 
+// Round-to-nearest-even BF16 (the upper 16 bits of an FP32) of a finite float.
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_to_f32(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+// Relative error bound of a split-BF16 H-term dot product (hi/lo parts of
+// both operands, the three cross products hi*hi + hi*lo + lo*hi accumulated
+// in FP32), against sum |w||x|: each operand is w = hi + lo + dw with
+// |lo| <= u_b (1 + u_b) |w| and |dw| <= u_b^2 |w| (u_b = 2^-8, round to
+// nearest), so the dropped lo*lo and the residual terms stay below
+// 3 u_b^2 (1 + 2 u_b) |w||x|; the 3H exact products are then summed in FP32.
+double split_const(int H) {
+  const double ub = ldexp(1.0, -8);
+  return 3.0 * ub * ub * (1.0 + 2.0 * ub) * (1.0 + 1e-6) + dot_const(3 * H, 24);
+}
+
 bool finite_all(const float* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!isfinite(p[i])) return false;
@@ -107,13 +133,36 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
       ebh[(size_t)(l - 1) * H + r] = up_f32(cK * fabs((double)bv) + eta);
     }
   }
+  // split-BF16 copy of the hidden layers for SPK_PREC_BF16X3, in the A
+  // operand order of the 16x16x32 BF16 MFMA: [t2][tp][lane] = (8 hi, 8 lo)
+  // for W[16 tp + c][32 t2 + 8 g + i], i = 0..7 (hi = RNE(W), lo = RNE(W - hi))
+  const int MT2 = MT / 2;
+  const size_t nWb = (size_t)(L - 2) * H * H * 2;   // uint16 count (hi + lo)
+  std::vector<uint16_t> Wb(nWb);
+  for (int l = 1; l <= L - 2; ++l) {
+    const float* Wl = W[l];
+    uint16_t* dst = Wb.data() + (size_t)(l - 1) * H * H * 2;
+    for (int t2 = 0; t2 < MT2; ++t2)
+      for (int tp = 0; tp < MT; ++tp)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int g = lane >> 4, c = lane & 15;
+          uint16_t* o = dst + (((size_t)t2 * MT + tp) * 64 + lane) * 16;
+          for (int i = 0; i < 8; ++i) {
+            const float w = Wl[(size_t)(16 * tp + c) * H + 32 * t2 + 8 * g + i];
+            const uint16_t hi = bf16_rne(w);
+            o[i] = hi;
+            o[8 + i] = bf16_rne(w - bf16_to_f32(hi));
+          }
+        }
+  }
   for (int r = 0; r < H; ++r) wL[r] = W[L - 1][r];
   const float bL = b[L - 1][0];
 
   // one device block, 256-byte aligned pieces
   auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
   const size_t oW0 = 0, ob0 = oW0 + al(nW0 * 4), oWp = ob0 + al(nb0 * 4), obh = oWp + al(nWp * 4 + 4),
-               oebh = obh + al(nbh * 4 + 4), owL = oebh + al(nbh * 4 + 4), total = owL + al((size_t)H * 4);
+               oebh = obh + al(nbh * 4 + 4), owL = oebh + al(nbh * 4 + 4), oWb = owL + al((size_t)H * 4),
+               total = oWb + al(nWb * 2 + 4);
   std::vector<unsigned char> img(total, 0);
   memcpy(img.data() + oW0, W0.data(), nW0 * 4);
   memcpy(img.data() + ob0, b0.data(), nb0 * 4);
@@ -123,6 +172,7 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
     memcpy(img.data() + oebh, ebh.data(), nbh * 4);
   }
   memcpy(img.data() + owL, wL.data(), (size_t)H * 4);
+  if (nWb) memcpy(img.data() + oWb, Wb.data(), nWb * 2);
 
   spk_net* net = new (std::nothrow) spk_net();
   if (net == nullptr) return SPK_E_NOMEM;
@@ -151,6 +201,8 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   d.bh = (const float*)(base + obh);
   d.ebh = (const float*)(base + oebh);
   d.wL = (const float*)(base + owL);
+  d.Wb = (const uint32_t*)(base + oWb);
+  d.cKs = up_f32(split_const(H));
   net->dev_block = blk;
   net->n_linear = n_linear;
   net->width = H;
@@ -241,7 +293,8 @@ spk_status spk_range_bound(spk_ctx* ctx, const spk_net* net, const spk_bound_opt
   job.s = s;
   job.policy = opts->policy;
   job.k = opts->k;
-  job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
+  job.prec = opts->prec;
+  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
   job.a = center;
   job.b = axes;
   job.lo = lo;
@@ -266,7 +319,8 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
   job.s = 3;
   job.policy = opts->policy;
   job.k = opts->k;
-  job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
+  job.prec = opts->prec;
+  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
   job.a = box_lo;
   job.b = box_hi;
   job.lo = lo;
@@ -302,7 +356,8 @@ spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bo
   job.s = 3;
   job.policy = opts->policy;
   job.k = opts->k;
-  job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
+  job.prec = opts->prec;
+  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
   job.cells = cells;
   job.level = level;
   for (int d = 0; d < 3; ++d) {
@@ -431,7 +486,8 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
     job.s = 3;
     job.policy = opts->policy;
     job.k = opts->k;
-    job.rigorous = (opts->flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
+    job.prec = opts->prec;
+  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
     job.cells = (const uint64_t*)codes;
     job.level = level;
     for (int d = 0; d < 3; ++d) {

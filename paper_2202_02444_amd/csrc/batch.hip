@@ -175,6 +175,7 @@ spk_status write_descriptors(spk_batch* b, const spk_batch_item* items, hipStrea
       job.policy = b->opts.policy;
       job.k = b->opts.k;
       job.rigorous = (b->opts.flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
+      job.prec = SPK_PREC_F32;
       job.a = it.box_lo;
       job.b = it.box_hi;
       job.lo = it.lo;
@@ -264,6 +265,7 @@ spk_status spk_batch_create(spk_ctx* ctx, const spk_bound_opts* opts, int32_t n_
   if (ctx == nullptr || out == nullptr || n_items <= 0 || items == nullptr) return SPK_E_INVAL;
   spk_status st = spk::valid_opts(opts);
   if (st != SPK_OK) return st;
+  if (opts->prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;   // the class kernels are FP32
   for (int i = 0; i < n_items; ++i) {
     st = valid_item(items[i]);
     if (st != SPK_OK) return st;

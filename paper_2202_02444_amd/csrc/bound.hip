@@ -18,49 +18,55 @@
 
 namespace spk {
 
-template <class S, int ACT, int POL>
+template <class S, int ACT, int POL, int PREC>
 __global__ __launch_bounds__(64, 1) void bound_kernel(NetDev net, BoundJob job) {
   __shared__ __attribute__((aligned(16))) LdsState<S> sm;
   const int64_t ngroups = (job.n + S::BPW - 1) / S::BPW;
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x)
-    bound_group<S, ACT, POL>(net, job, sm, grp, (int)threadIdx.x);
+    bound_group<S, ACT, POL, PREC>(net, job, sm, grp, (int)threadIdx.x);
 }
 
-template <class S, int ACT, int POL>
+template <class S, int ACT, int POL, int PREC>
 static hipError_t launch_one(const NetDev& net, const BoundJob& job, hipStream_t stream, int num_cus) {
   const int64_t ngroups = (job.n + S::BPW - 1) / S::BPW;
   int64_t blocks = (int64_t)num_cus * 4;
   if (blocks > ngroups) blocks = ngroups;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((bound_kernel<S, ACT, POL>), dim3((unsigned)blocks), dim3(64), 0, stream, net, job);
+  hipLaunchKernelGGL((bound_kernel<S, ACT, POL, PREC>), dim3((unsigned)blocks), dim3(64), 0, stream, net, job);
   return hipGetLastError();
 }
 
-template <int H, int NT, int POL>
+template <int H, int NT, int POL, int PREC>
 static hipError_t launch_act(const NetDev& net, const BoundJob& job, hipStream_t stream, int num_cus) {
   switch (net.act) {
-    case SPK_ACT_RELU: return launch_one<Shape<H, NT>, SPK_ACT_RELU, POL>(net, job, stream, num_cus);
-    case SPK_ACT_ELU: return launch_one<Shape<H, NT>, SPK_ACT_ELU, POL>(net, job, stream, num_cus);
-    case SPK_ACT_SIN: return launch_one<Shape<H, NT>, SPK_ACT_SIN, POL>(net, job, stream, num_cus);
+    case SPK_ACT_RELU: return launch_one<Shape<H, NT>, SPK_ACT_RELU, POL, PREC>(net, job, stream, num_cus);
+    case SPK_ACT_ELU: return launch_one<Shape<H, NT>, SPK_ACT_ELU, POL, PREC>(net, job, stream, num_cus);
+    case SPK_ACT_SIN: return launch_one<Shape<H, NT>, SPK_ACT_SIN, POL, PREC>(net, job, stream, num_cus);
   }
   return hipErrorInvalidValue;
 }
 
-template <int H>
+template <int H, int PREC>
 static hipError_t launch_h(const NetDev& net, const BoundJob& job, hipStream_t stream, int num_cus) {
-  if (job.policy == SPK_AFFINE_FIXED) return launch_act<H, 1, SPK_AFFINE_FIXED>(net, job, stream, num_cus);
-  if (job.k <= 15) return launch_act<H, 1, SPK_AFFINE_TRUNCATE>(net, job, stream, num_cus);
-  return launch_act<H, 2, SPK_AFFINE_TRUNCATE>(net, job, stream, num_cus);
+  if (job.policy == SPK_AFFINE_FIXED) return launch_act<H, 1, SPK_AFFINE_FIXED, PREC>(net, job, stream, num_cus);
+  if (job.k <= 15) return launch_act<H, 1, SPK_AFFINE_TRUNCATE, PREC>(net, job, stream, num_cus);
+  return launch_act<H, 2, SPK_AFFINE_TRUNCATE, PREC>(net, job, stream, num_cus);
 }
 
 spk_status launch_bound(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus) {
   if (job.n <= 0) return SPK_OK;
   hipError_t err;
+  if (job.prec == SPK_PREC_BF16X3) {
+    // split-BF16 products are built for one box per wave (hidden width 256)
+    if (net->dev.H != 256) return SPK_E_UNSUPPORTED;
+    err = launch_h<256, SPK_PREC_BF16X3>(net->dev, job, stream, num_cus);
+    return err == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+  }
   switch (net->dev.H) {
-    case 32: err = launch_h<32>(net->dev, job, stream, num_cus); break;
-    case 64: err = launch_h<64>(net->dev, job, stream, num_cus); break;
-    case 128: err = launch_h<128>(net->dev, job, stream, num_cus); break;
-    case 256: err = launch_h<256>(net->dev, job, stream, num_cus); break;
+    case 32: err = launch_h<32, SPK_PREC_F32>(net->dev, job, stream, num_cus); break;
+    case 64: err = launch_h<64, SPK_PREC_F32>(net->dev, job, stream, num_cus); break;
+    case 128: err = launch_h<128, SPK_PREC_F32>(net->dev, job, stream, num_cus); break;
+    case 256: err = launch_h<256, SPK_PREC_F32>(net->dev, job, stream, num_cus); break;
     default: return SPK_E_UNSUPPORTED;
   }
   return err == hipSuccess ? SPK_OK : SPK_E_DEVICE;

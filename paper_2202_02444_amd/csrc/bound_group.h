@@ -46,7 +46,7 @@ __device__ __forceinline__ void box_input(const BoundJob& job, int64_t box, bool
   }
 }
 
-template <class S, int ACT, int POL>
+template <class S, int ACT, int POL, int PREC = SPK_PREC_F32>
 __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& job, LdsState<S>& sm, int64_t grp,
                                             int lane) {
   constexpr int NS = S::NS, BPW = S::BPW, SEG = S::SEG;
@@ -66,9 +66,11 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
   for (int a = 0; a < L - 1; ++a) {
     int16_t* rec = nullptr;
     if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
-    n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, net.cK, net.cD, net.omega0, lane, rec);
+    // the next layer's generator products: FP32 or split-BF16 rounding bound
+    const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs : net.cK;
+    n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec);
     if (a == L - 2) break;
-    hidden_layer<S, 0>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
+    hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
   }
   float pass[1];
   const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass);

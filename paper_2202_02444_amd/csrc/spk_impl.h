@@ -30,6 +30,8 @@ struct NetDev {
   const float* bh;   // (L-2) * H biases
   const float* ebh;  // (L-2) * H : cK * |b| + absolute slack, rounded up
   const float* wL;   // [H] output weights
+  const uint32_t* Wb;  // (L-2) hidden layers as split BF16 (hi, lo) in 16x16x32 MFMA A-operand order
+  float cKs;          // relative rounding bound of a split-BF16 H-term dot product (SPK_PREC_BF16X3)
 };
 
 // Input of a bound launch: which box source feeds the first layer.
@@ -42,6 +44,7 @@ struct BoundJob {
   int policy;         // spk_policy (fixed or truncate)
   int k;              // kept terms (truncate)
   int rigorous;       // 1: lo/hi use the rigorous rounding radius
+  int prec;           // spk_prec of the generator products
   // IN_AABB: a = lo [n][3], b = hi [n][3]; IN_GENERAL: a = center [n][3], b = axes [n][s][3]
   const float* a;
   const float* b;
@@ -124,7 +127,7 @@ namespace spk {
 // Validation of the bound options shared by every entry point.
 inline spk_status valid_opts(const spk_bound_opts* o) {
   if (o == nullptr) return SPK_E_INVAL;
-  if (o->prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;
+  if (o->prec != SPK_PREC_F32 && o->prec != SPK_PREC_BF16X3) return SPK_E_UNSUPPORTED;
   if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
   if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
   if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;

@@ -134,8 +134,11 @@ def _ptr(t, dtype=None, shape=None, name="tensor"):
 FLAG_RIGOROUS = 1
 
 
-def opts(policy="truncate", k=31, rigorous=False):
-    return BoundOpts(POLICY[policy], int(k), 0, FLAG_RIGOROUS if rigorous else 0)
+PREC = {"f32": 0, "bf16x3": 1}
+
+
+def opts(policy="truncate", k=31, rigorous=False, prec="f32"):
+    return BoundOpts(POLICY[policy], int(k), PREC[prec], FLAG_RIGOROUS if rigorous else 0)
 
 
 class Net:
@@ -209,10 +212,10 @@ def _aux(center=None, radius=None, err=None, slot_src=None):
 
 
 def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="truncate", k=31, aux=None,
-                   rigorous=False):
+                   rigorous=False, prec="f32"):
     import torch
     n = box_lo.shape[0]
-    o = opts(policy, k, rigorous)
+    o = opts(policy, k, rigorous, prec)
     a = _aux(**aux) if aux else None
     st = lib().spk_classify_boxes(ctx.handle, net.handle, ctypes.byref(o), n,
                                   _ptr(box_lo, torch.float32, (n, 3), "box_lo"),
@@ -223,10 +226,10 @@ def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="tr
     _check(st, "spk_classify_boxes")
 
 
-def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=None, rigorous=False):
+def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=None, rigorous=False, prec="f32"):
     import torch
     n, s = axes.shape[0], axes.shape[1]
-    o = opts(policy, k, rigorous)
+    o = opts(policy, k, rigorous, prec)
     a = _aux(**aux) if aux else None
     st = lib().spk_range_bound(ctx.handle, net.handle, ctypes.byref(o), n, s,
                                _ptr(center, torch.float32, (n, 3), "center"),

@@ -16,7 +16,7 @@ def s_net(net, n=4096, seed=1234):
     return float(np.sqrt(np.mean(f * f)))
 
 
-def gpu_classify(ctx, g, lo, hi, policy, k, want_src=False, rigorous=False):
+def gpu_classify(ctx, g, lo, hi, policy, k, want_src=False, rigorous=False, prec="f32"):
     import torch
     from paper_2202_02444_amd import spk
     dev = torch.device("cuda")
@@ -34,7 +34,7 @@ def gpu_classify(ctx, g, lo, hi, policy, k, want_src=False, rigorous=False):
     if want_src:
         src = torch.full((g.n_linear - 1, n, 32), -3, dtype=torch.int16, device=dev)
         aux["slot_src"] = src
-    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, policy, k, aux=aux, rigorous=rigorous)
+    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, policy, k, aux=aux, rigorous=rigorous, prec=prec)
     ctx.sync()
     out = {"label": lab.cpu().numpy(), "lo": glo.cpu().numpy().astype(np.float64),
            "hi": ghi.cpu().numpy().astype(np.float64), "center": cen.cpu().numpy().astype(np.float64),
