@@ -68,6 +68,8 @@ def propagate(net, x0, X, xinf, policy="truncate", k=31, keep_sets=None, record=
             x0, X, xinf, keep, src = aa.condense_truncate(z0, Z, zinf, gamma, k, keep=keep)
             info["keep"] = keep
             info["src"] = src
+            # candidate magnitudes (old columns, then new terms) for top-k checks
+            info["mu"] = np.concatenate([np.abs(Z).sum(axis=1), gamma], axis=1)
         if record is not None:
             record.append(info)
     return x0[:, 0], X[:, 0, :], xinf[:, 0]

@@ -96,3 +96,18 @@ def soundness_violations(net, lo, hi, glo, ghi, rng, n_rand=8):
 
 def oracle_labels(lo_o, hi_o):
     return oq.classify(lo_o, hi_o)
+
+
+def valid_topk(record, rel=1e-5):
+    """Whether each replayed kept set is a valid top-k of the FP64 candidate
+    magnitudes: every kept magnitude is at least every dropped one, up to
+    rel times the largest.  Returns the number of (layer, box) violations."""
+    bad = 0
+    for info in record:
+        keep, mu = info["keep"], info["mu"]
+        if keep.all():
+            continue
+        big = np.where(keep, mu, np.inf).min(axis=1)
+        small = np.where(keep, -np.inf, mu).max(axis=1)
+        bad += int(np.sum(big < small - rel * mu.max(axis=1)))
+    return bad

@@ -10,7 +10,7 @@ import workloads as wl
 from oracle import mlp as omlp
 
 from parity import (TOL, default_margin, endpoint_errors, gpu_classify, keep_sets_from_src, label_ambiguous,
-                    oracle_labels, s_net, soundness_violations)
+                    oracle_labels, s_net, soundness_violations, valid_topk)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,8 @@ def _run(ctx, net, lo, hi, policy, k, replay=True, sound_rng=None):
         res["replay"] = endpoint_errors(out["center"], out["radius"], lo_r, hi_r, S)
         res["replay_bounds"] = (lo_r, hi_r)
         res["sets"] = sets
+        # the GPU's kept sets are valid top-k selections of the FP64 magnitudes
+        res["topk_violations"] = valid_topk(rec)
     if sound_rng is not None:
         res["violations"], _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], sound_rng)
     return res
@@ -70,6 +72,7 @@ def test_tiny_truncate(ctx, k):
     lo, hi = wl.boxes(4096, 10, 1e-3, 0.25)
     r = _run(ctx, net, lo, hi, "truncate", k, sound_rng=np.random.default_rng(2))
     assert r["replay"].max() <= TOL, r["replay"].max()
+    assert r["topk_violations"] == 0
     assert (r["free"] <= TOL).mean() >= 0.99
     assert r["violations"] == 0
     lo_r, hi_r = r["replay_bounds"]
@@ -85,6 +88,7 @@ def test_ragged_sizes(ctx, n):
         lo, hi = wl.boxes(n, 20 + n, 1e-3, 0.3)
         r = _run(ctx, net, lo, hi, "truncate", 31, sound_rng=np.random.default_rng(n))
         assert r["replay"].max() <= TOL, (H, r["replay"].max())
+        assert r["topk_violations"] == 0, H
         assert r["violations"] == 0
 
 

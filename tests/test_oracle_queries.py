@@ -170,3 +170,33 @@ def test_closest_point_octahedron():
         assert best >= dstar - 1e-12
         assert dstar - diag / 2 - 1e-12 <= dist <= dstar + diag + 1e-12
         assert abs(np.abs(pt).sum() - R) <= math.sqrt(3.0) * diag / 2 + 1e-12
+
+
+def test_valid_topk_detects_a_wrong_kept_set():
+    """The top-k validity check used by the GPU tests: the oracle's own
+    selection passes; keeping the smallest dropped candidate instead of the
+    smallest kept one (strictly larger) fails."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from parity import valid_topk
+    from oracle import mlp as omlp
+    net = wl.tiny_net(0)
+    lo, hi = wl.boxes(64, 3, 1e-3, 0.2)
+    rec = []
+    omlp.bound_boxes(net, lo, hi, "truncate", 8, record=rec)
+    assert valid_topk(rec) == 0
+    mu = rec[0]["mu"]
+    keep = rec[0]["keep"]
+    b = int(np.argmax([mu[i, keep[i]].min() - mu[i, ~keep[i]].min() for i in range(len(mu))]))
+    kept = np.flatnonzero(keep[b])
+    dropped = np.flatnonzero(~keep[b])
+    i_small = kept[np.argmin(mu[b, kept])]
+    i_low = dropped[np.argmin(mu[b, dropped])]
+    assert mu[b, i_low] < mu[b, i_small]
+    sets = [r["keep"].copy() for r in rec]
+    sets[0][b, i_small] = False
+    sets[0][b, i_low] = True
+    rec2 = []
+    omlp.bound_boxes(net, lo, hi, "truncate", 8, keep_sets=sets, record=rec2)
+    assert valid_topk(rec2) >= 1
