@@ -288,6 +288,66 @@ spk_status spk_batch_tune(spk_ctx* ctx, spk_batch* batch, int32_t reps);
 spk_status spk_batch_classes(const spk_batch* batch, int32_t* n_classes, spk_batch_class* out, int32_t cap);
 spk_status spk_batch_destroy(spk_batch* batch);
 
+/*
+ * Serving: continuous batching of requests against device-resident networks.
+ * A server owns n_workers worker threads, each with its own HIP stream and
+ * context.  Requests queue in FIFO order; the head request is admitted as soon
+ * as a worker is free and the declared bytes of the requests in flight plus
+ * its own fit mem_budget (a request larger than the budget runs alone).
+ * Admitted requests run side by side on their streams; each one makes exactly
+ * the calls a standalone caller would make, so its result does not depend on
+ * the mix.  The server never allocates request buffers: the caller allocates
+ * inputs and outputs (device memory) and keeps them alive until the request's
+ * completion is returned by spk_server_poll.
+ *
+ * spk_request fields by type:
+ *   SPK_REQ_CLASSIFY  a = box_lo, b = box_hi [n][3]; out0 = label (uint8 [n]),
+ *                     out1 = lo, out2 = hi (float [n], nullable); opts.
+ *   SPK_REQ_RAYS      a = origin, b = dir [n][3]; out0 = t_hit (float [n]),
+ *                     out1 = iters (int32 [n], nullable); ray.
+ *   SPK_REQ_CLOSEST   a = query [n][3]; out0 = point [n][3], out1 = dist,
+ *                     out2 = bound (float [n], nullable); opts, tree.
+ *   bytes             the request's device footprint as the caller counts it
+ *                     (inputs + outputs + an estimate of library workspace);
+ *                     used only for admission.
+ * spk_server_poll returns up to max completions (wait != 0: block until one is
+ * available or nothing is queued or running).  spk_server_destroy waits for
+ * every queued and running request, then stops the workers.
+ */
+typedef enum { SPK_REQ_CLASSIFY = 0, SPK_REQ_RAYS = 1, SPK_REQ_CLOSEST = 2 } spk_req_type;
+
+typedef struct {
+  int32_t type;              /* spk_req_type                                   */
+  int32_t net;               /* index into the server's network list           */
+  int64_t n;
+  const float* a;
+  const float* b;
+  void* out0;
+  void* out1;
+  void* out2;
+  size_t bytes;
+  spk_bound_opts opts;
+  spk_ray_params ray;
+  spk_tree_params tree;
+} spk_request;
+
+typedef struct {
+  uint64_t id;
+  int32_t status;            /* spk_status of the request                      */
+  int32_t type;
+  int64_t n;
+  double submit_s, start_s, done_s;   /* steady-clock seconds                  */
+} spk_completion;
+
+typedef struct spk_server spk_server;
+
+spk_status spk_server_create(const spk_net* const* nets, int32_t n_nets, size_t mem_budget, int32_t n_workers,
+                             spk_server** out);
+spk_status spk_server_submit(spk_server* server, const spk_request* req, uint64_t* id);
+spk_status spk_server_poll(spk_server* server, spk_completion* out, int32_t max, int32_t* n_done, int32_t wait);
+spk_status spk_server_pending(spk_server* server, int32_t* queued, int32_t* running, size_t* bytes_in_flight);
+spk_status spk_server_destroy(spk_server* server);
+
 /* Point evaluation f(x) for x dev [n][3] -> f dev [n] (FP32). */
 spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f);
 

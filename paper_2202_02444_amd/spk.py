@@ -24,7 +24,8 @@ EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
            "spk_subdivide_frontier", "spk_cast_rays", "spk_eval_points", "spk_closest_point",
            "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
-           "spk_batch_destroy")
+           "spk_batch_destroy", "spk_server_create", "spk_server_submit", "spk_server_poll",
+           "spk_server_pending", "spk_server_destroy")
 
 
 class BatchItem(ctypes.Structure):
@@ -37,6 +38,16 @@ class BatchClass(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("act", ctypes.c_int32), ("term_slots", ctypes.c_int32),
                 ("n_nets", ctypes.c_int32), ("groups", ctypes.c_int64), ("blocks", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("tuned_ms", ctypes.c_float)]
+
+
+class Request(ctypes.Structure):
+    pass
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("type", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
 
 
 class BoundOpts(ctypes.Structure):
@@ -59,6 +70,13 @@ class RayParams(ctypes.Structure):
                 ("eta_minus", ctypes.c_float), ("eta_plus", ctypes.c_float), ("safety", ctypes.c_float),
                 ("max_iters", ctypes.c_int32), ("clip_to_domain", ctypes.c_int32)]
 
+
+Request._fields_ = [("type", ctypes.c_int32), ("net", ctypes.c_int32), ("n", ctypes.c_int64),
+                    ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("out0", ctypes.c_void_p),
+                    ("out1", ctypes.c_void_p), ("out2", ctypes.c_void_p), ("bytes", ctypes.c_size_t),
+                    ("opts", BoundOpts), ("ray", RayParams), ("tree", TreeParams)]
+
+REQ_CLASSIFY, REQ_RAYS, REQ_CLOSEST = 0, 1, 2
 
 _lib = None
 
@@ -96,6 +114,11 @@ def lib():
         L.spk_batch_tune.argtypes = [vp, vp, i32]
         L.spk_batch_classes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(BatchClass), i32]
         L.spk_batch_destroy.argtypes = [vp]
+        L.spk_server_create.argtypes = [ctypes.POINTER(vp), i32, sz, i32, ctypes.POINTER(vp)]
+        L.spk_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.spk_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32), i32]
+        L.spk_server_pending.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
+        L.spk_server_destroy.argtypes = [vp]
         L.spk_closest_point.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i64, vp, vp,
                                         vp, vp]
         for name in EXPORTS:
@@ -338,6 +361,89 @@ class Batch:
         if self.handle:
             _check(lib().spk_batch_destroy(self.handle), "spk_batch_destroy")
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """spk_server_*: continuous batching over resident networks.  Requests are
+    dicts: {"type": "classify"|"rays"|"closest", "net": index, tensors...};
+    the caller keeps every tensor alive until its completion is polled and
+    must have finished writing the inputs (e.g. torch.cuda.synchronize())
+    before submitting."""
+
+    TYPES = {"classify": REQ_CLASSIFY, "rays": REQ_RAYS, "closest": REQ_CLOSEST}
+
+    def __init__(self, nets, mem_budget, n_workers=4):
+        self.handle = None
+        arr = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
+        h = ctypes.c_void_p()
+        _check(lib().spk_server_create(arr, len(nets), int(mem_budget), int(n_workers), ctypes.byref(h)),
+               "spk_server_create")
+        self.handle = h
+        self._live = {}
+
+    def submit(self, req):
+        import torch
+
+        def v(t):
+            return None if t is None else t.data_ptr()
+        r = Request()
+        r.type = self.TYPES[req["type"]]
+        r.net = int(req["net"])
+        if req["type"] == "classify":
+            r.n = req["box_lo"].shape[0]
+            r.a, r.b = v(req["box_lo"]), v(req["box_hi"])
+            r.out0, r.out1, r.out2 = v(req["label"]), v(req.get("lo")), v(req.get("hi"))
+            r.opts = opts(req.get("policy", "truncate"), req.get("k", 31))
+            tensors = [req["box_lo"], req["box_hi"], req["label"], req.get("lo"), req.get("hi")]
+        elif req["type"] == "rays":
+            r.n = req["origin"].shape[0]
+            r.a, r.b = v(req["origin"]), v(req["dir"])
+            r.out0, r.out1 = v(req["t_hit"]), v(req.get("iters"))
+            r.ray = ray_params(**req.get("params", {}))
+            tensors = [req["origin"], req["dir"], req["t_hit"], req.get("iters")]
+        else:
+            r.n = req["q"].shape[0]
+            r.a = v(req["q"])
+            r.out0, r.out1, r.out2 = v(req["point"]), v(req.get("dist")), v(req.get("bound"))
+            r.opts = opts(req.get("policy", "fixed"), req.get("k", 31))
+            r.tree = TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1),
+                                int(req.get("max_level", 8)), 8)
+            tensors = [req["q"], req["point"], req.get("dist"), req.get("bound")]
+        r.bytes = int(req.get("bytes", sum(t.numel() * t.element_size() for t in tensors if t is not None)))
+        rid = ctypes.c_uint64()
+        _check(lib().spk_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)), "spk_server_submit")
+        self._live[rid.value] = tensors
+        return rid.value
+
+    def poll(self, max_n=64, wait=False):
+        out = (Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().spk_server_poll(self.handle, out, max_n, ctypes.byref(n), 1 if wait else 0), "spk_server_poll")
+        res = []
+        for i in range(n.value):
+            c = out[i]
+            self._live.pop(c.id, None)
+            res.append({"id": c.id, "status": c.status, "type": c.type, "n": c.n, "submit_s": c.submit_s,
+                        "start_s": c.start_s, "done_s": c.done_s})
+        return res
+
+    def pending(self):
+        q, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(lib().spk_server_pending(self.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)),
+               "spk_server_pending")
+        return q.value, r.value, b.value
+
+    def close(self):
+        if self.handle:
+            _check(lib().spk_server_destroy(self.handle), "spk_server_destroy")
+            self.handle = None
+            self._live.clear()
 
     def __del__(self):
         try:

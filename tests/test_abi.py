@@ -143,3 +143,43 @@ def test_batch_validation():
     assert L.spk_batch_destroy(None) == spk.E_INVAL
     n = ctypes.c_int32()
     assert L.spk_batch_classes(None, ctypes.byref(n), None, 0) == spk.E_INVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of every ABI struct have the C compiler's size and
+    field offsets (a plain C program built against include/spk.h)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"spk_bound_opts": spk.BoundOpts, "spk_bound_aux": spk.BoundAux, "spk_tree_params": spk.TreeParams,
+               "spk_ray_params": spk.RayParams, "spk_batch_item": spk.BatchItem, "spk_batch_class": spk.BatchClass,
+               "spk_request": spk.Request, "spk_completion": spk.Completion}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "spk.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
+
+
+def test_server_validation():
+    L = spk.lib()
+    h = ctypes.c_void_p()
+    assert L.spk_server_create(None, 1, 0, 4, ctypes.byref(h)) == spk.E_INVAL
+    nets = (ctypes.c_void_p * 1)(0x1000)
+    assert L.spk_server_create(nets, 1, 0, 0, ctypes.byref(h)) == spk.E_INVAL       # no workers
+    assert L.spk_server_submit(None, None, None) == spk.E_INVAL
+    n = ctypes.c_int32()
+    assert L.spk_server_poll(None, None, 0, ctypes.byref(n), 0) == spk.E_INVAL
+    assert L.spk_server_destroy(None) == spk.E_INVAL
