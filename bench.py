@@ -166,6 +166,84 @@ def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, n_sample=2048, steps=2):
     return res
 
 
+def serving_extra(dev, n_requests=60, load=0.6, seed=500):
+    """Poisson arrivals of ray-cast, box-classify and closest-point requests
+    (40/40/20 %) against 16 resident networks, served by 4 workers under a
+    16 GB admission budget; p50/p99 latency per request type.  Sizes are
+    log-uniform (boxes 1e3-2.5e5, rays 1e3-1.6e4, closest 2.5e2-4e3 at level 8);
+    rays and closest points target the small nets, whose affine-fixed bounds
+    keep ray marches and tree searches short."""
+    import torch
+    import workloads as wl
+    from paper_2202_02444_amd import spk
+    specs = [wl.tiny_net(i) for i in range(4)] + [wl.scale_net(i) for i in range(1, 5)] + \
+        [n for j, n in enumerate(wl.batched_nets(24)) if j % 3 == 0][:8]
+    nets = [spk.Net.from_spec(s_) for s_ in specs]
+    rng = np.random.default_rng(seed)
+
+    def logu(lo_, hi_):
+        return int(round(math.exp(rng.uniform(math.log(lo_), math.log(hi_)))))
+    reqs = []
+    for i in range(n_requests):
+        u = rng.uniform()
+        if u < 0.4:
+            n = logu(1e3, 2.5e5)
+            lo, hi = wl.boxes(n, 5000 + i, 1e-4, 0.5)
+            reqs.append({"type": "classify", "net": int(rng.integers(0, 16)), "box_lo": torch.from_numpy(lo).to(dev),
+                         "box_hi": torch.from_numpy(hi).to(dev), "label": torch.empty(n, dtype=torch.uint8, device=dev)})
+        elif u < 0.8:
+            side = max(32, int(round(math.sqrt(logu(1e3, 1.6e4)))))
+            o, d = wl.camera_rays(side, side, 5000 + i)
+            reqs.append({"type": "rays", "net": int(rng.integers(0, 4)), "origin": torch.from_numpy(o).to(dev),
+                         "dir": torch.from_numpy(d).to(dev), "t_hit": torch.empty(o.shape[0], device=dev)})
+        else:
+            n = logu(250, 4000)
+            reqs.append({"type": "closest", "net": int(rng.integers(0, 4)),
+                         "q": torch.from_numpy(wl.points(n, 5000 + i)).to(dev),
+                         "point": torch.empty((n, 3), device=dev), "dist": torch.empty(n, device=dev),
+                         "max_level": 8})
+    torch.cuda.synchronize()
+    # capacity: all requests back to back through one worker
+    srv = spk.Server(nets, 16 << 30, 1)
+    t0 = time.perf_counter()
+    for r in reqs:
+        srv.submit(r)
+    n_done = 0
+    while n_done < len(reqs):
+        n_done += len(srv.poll(64, wait=True))
+    busy = time.perf_counter() - t0
+    srv.close()
+    # open-loop Poisson arrivals at `load` of that capacity, 4 workers
+    rate = load * len(reqs) / busy
+    gaps = rng.exponential(1.0 / rate, len(reqs))
+    srv = spk.Server(nets, 16 << 30, 4)
+    done = []
+    t0 = time.perf_counter()
+    arrive = t0 + np.cumsum(gaps)
+    for r, ta in zip(reqs, arrive):
+        while True:
+            done += srv.poll(64)
+            dt = ta - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.002))
+        srv.submit(r)
+    while len(done) < len(reqs):
+        done += srv.poll(64, wait=True)
+    wall = time.perf_counter() - t0
+    srv.close()
+    names = {0: "classify", 1: "rays", 2: "closest"}
+    out = {"requests": len(reqs), "workers": 4, "offered_load": load, "wall_s": wall,
+           "ok": int(sum(c["status"] == 0 for c in done))}
+    for t, name in names.items():
+        lat = np.array([(c["done_s"] - c["submit_s"]) * 1e3 for c in done if c["type"] == t])
+        if lat.size:
+            out[name] = {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)),
+                         "items_per_s": float(sum(c["n"] for c in done if c["type"] == t) / wall)}
+    return out
+
+
 def cpu_baseline(net, lo, hi, n_sample):
     """The FP64 oracle, as it stands, on a bounded sample of the same boxes."""
     from oracle import mlp as omlp
@@ -303,6 +381,8 @@ def main():
         progress("batched done")
         extra["precision"] = precision_extra(ctx, g, net, tlo, thi, lo, hi, dev)
         progress("precision done")
+        extra["serving"] = serving_extra(dev)
+        progress("serving done")
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, lo, hi, args.cpu_sample)
