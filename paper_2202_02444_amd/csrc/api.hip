@@ -155,6 +155,19 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
           }
         }
   }
+  // 4x4 blocks of the hidden layers for row-owner products (packed ray
+  // kernel): Wr[l][kb][rb][i][j] = W[4 rb + i][4 kb + j], so lane rb's four
+  // rows at one k step are 64 contiguous bytes and a wave's step is one
+  // contiguous H*16-byte block
+  std::vector<float> Wr(nWp);
+  for (int l = 1; l <= L - 2; ++l) {
+    float* dst = Wr.data() + (size_t)(l - 1) * H * H;
+    for (int kb = 0; kb < H / 4; ++kb)
+      for (int rb = 0; rb < H / 4; ++rb)
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j)
+            dst[(((size_t)kb * (H / 4) + rb) * 4 + i) * 4 + j] = W[l][(size_t)(4 * rb + i) * H + 4 * kb + j];
+  }
   for (int r = 0; r < H; ++r) wL[r] = W[L - 1][r];
   const float bL = b[L - 1][0];
 
@@ -162,7 +175,7 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
   const size_t oW0 = 0, ob0 = oW0 + al(nW0 * 4), oWp = ob0 + al(nb0 * 4), obh = oWp + al(nWp * 4 + 4),
                oebh = obh + al(nbh * 4 + 4), owL = oebh + al(nbh * 4 + 4), oWb = owL + al((size_t)H * 4),
-               total = oWb + al(nWb * 2 + 4);
+               oWr = oWb + al(nWb * 2 + 4), total = oWr + al(nWp * 4 + 4);
   std::vector<unsigned char> img(total, 0);
   memcpy(img.data() + oW0, W0.data(), nW0 * 4);
   memcpy(img.data() + ob0, b0.data(), nb0 * 4);
@@ -173,6 +186,7 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   }
   memcpy(img.data() + owL, wL.data(), (size_t)H * 4);
   if (nWb) memcpy(img.data() + oWb, Wb.data(), nWb * 2);
+  if (nWp) memcpy(img.data() + oWr, Wr.data(), nWp * 4);
 
   spk_net* net = new (std::nothrow) spk_net();
   if (net == nullptr) return SPK_E_NOMEM;
@@ -203,6 +217,7 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   d.wL = (const float*)(base + owL);
   d.Wb = (const uint32_t*)(base + oWb);
   d.cKs = up_f32(split_const(H));
+  d.Wr = (const float*)(base + oWr);
   net->dev_block = blk;
   net->n_linear = n_linear;
   net->width = H;

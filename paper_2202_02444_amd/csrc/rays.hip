@@ -193,9 +193,328 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Packed ray marching for hidden width 256: one wavefront marches RPW rays
+// at once.  Each ray takes three term slots of one 16-slot tile (its segment
+// generator and its two passenger points), so one MFMA pass serves RPW rays.
+// The FP64 centers and |W| xinf of the RPW rays are row-owner dot products
+// (lane l owns rows 4l..4l+3) over a copy of W in 4x4 blocks (one coalesced
+// 4 KB load per wave and k step), sharing each weight conversion across the
+// rays.  Ray state is uniform across the wavefront.
+// ---------------------------------------------------------------------------
+constexpr int RPW = 5;
+
+template <class S>
+struct PackedRayLds {
+  LdsState<S> base;              // the 16-slot tile
+  float vinf[RPW][256];
+  double vc[RPW][256];
+};
+
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni(long long v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(unsigned long long)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Activation (affine-fixed) of every ray's rows; passengers get f exactly.
+template <int ACT>
+__device__ __forceinline__ void activate_packed(double (&xc)[RPW][4], f4 (&y)[16], float (&yinf)[RPW][4],
+                                                float omega0) {
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int G = 1 + 3 * r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      y[G + 1][i] = act_point<ACT>(y[G + 1][i], omega0);
+      y[G + 2][i] = act_point<ACT>(y[G + 2][i], omega0);
+      if (ACT == SPK_ACT_SIN) {
+        y[G][i] *= omega0;
+        yinf[r][i] *= omega0;
+        xc[r][i] *= (double)omega0;
+      }
+      const double x0 = xc[r][i];
+      const double rd = (double)fabsf(y[G][i]) + (double)yinf[r][i];
+      const ActOut p = act_params<ACT>(x0 - rd, x0 + rd, x0);
+      const float alf = (float)p.al;
+      y[G][i] *= alf;
+      xc[r][i] = fma(p.al, x0, p.be);
+      yinf[r][i] = fabsf(alf) * yinf[r][i] + fmaxf((float)p.ga, 0.0f);
+    }
+  }
+}
+
+// One H -> H layer for the packed rays.
+template <class S>
+__device__ __forceinline__ void hidden_packed(const NetDev& net, PackedRayLds<S>& sm, int a, double (&xc)[RPW][4],
+                                              f4 (&y)[16], float (&yinf)[RPW][4], int lane) {
+  constexpr int H = S::H;
+#pragma unroll
+  for (int C = 0; C < 16; ++C) *(f4*)&sm.base.tile[taddr<S>(0, C, lane)] = y[C];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    *(f4*)&sm.vinf[r][4 * lane] = (f4){yinf[r][0], yinf[r][1], yinf[r][2], yinf[r][3]};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sm.vc[r][4 * lane + i] = xc[r][i];
+  }
+  __syncthreads();
+  single_box_pass<S, VA_NONE>(sm.base, (const f4*)net.Wp + (size_t)a * (H * H / 4), 0, lane);
+  // row-owner products: centers (FP64) and |W| xinf of every ray
+  double pd[RPW][4];
+  float px[RPW][4];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      pd[r][i] = 0.0;
+      px[r][i] = 0.0f;
+    }
+  const f4* Wr = (const f4*)(net.Wr + (size_t)a * H * H) + 4 * lane;
+#pragma unroll 2
+  for (int k = 0; k < H; k += 4) {
+    f4 w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = Wr[(size_t)(k / 4) * H + i];
+    double wd[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wd[i][j] = (double)w[i][j];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const f4 xi = *(const f4*)&sm.vinf[r][k];
+      double xd[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xd[j] = sm.vc[r][k + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          pd[r][i] = fma(wd[i][j], xd[j], pd[r][i]);
+          px[r][i] = fmaf(fabsf(w[i][j]), xi[j], px[r][i]);
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int C = 1; C < 16; ++C) y[C] = *(const f4*)&sm.base.tile[taddr<S>(0, C, lane)];
+  const f4 bh = *(const f4*)&net.bh[(size_t)a * H + 4 * lane];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int G = 1 + 3 * r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xc[r][i] = pd[r][i] + (double)bh[i];
+      yinf[r][i] = px[r][i];
+      y[G + 1][i] += bh[i];
+      y[G + 2][i] += bh[i];
+    }
+  }
+  __syncthreads();
+}
+
+template <class S, int ACT>
+__global__ __launch_bounds__(64, 1) void ray_kernel_packed(NetDev net, RayJob job) {
+  static_assert(S::H == 256 && S::NT == 1, "packed rays: width 256, one 16-slot tile");
+  __shared__ __attribute__((aligned(16))) PackedRayLds<S> sm;
+  const int lane = threadIdx.x;
+  const int L = net.L;
+  const spk_ray_params P = job.p;
+
+  long long rid[RPW];
+  float t[RPW], sigma[RPW], f0[RPW], tmax[RPW], base[RPW], sp[RPW][3], dv[RPW][3];
+  int it[RPW], first[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    rid[r] = -1;
+    t[r] = sigma[r] = f0[r] = tmax[r] = base[r] = 0.0f;
+    it[r] = first[r] = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sp[r][a] = dv[r][a] = 0.0f;
+  }
+
+  for (;;) {
+    // ---- refill empty slots from the global counter (lane 0), broadcast
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (rid[r] != -1) continue;   // uniform
+      long long nr = -2;
+      float np[3] = {0.0f, 0.0f, 0.0f}, nd[3] = {0.0f, 0.0f, 0.0f}, ntmax = 0.0f, nbase = 0.0f;
+      if (lane == 0) {
+        for (;;) {
+          const unsigned long long idx = atomicAdd(job.counter, 1ull);
+          if (idx >= (unsigned long long)job.n) break;
+          float o[3], d[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            o[a] = job.origin[3 * idx + a];
+            d[a] = job.dir[3 * idx + a];
+          }
+          float t_in = 0.0f, t_out = P.t_max;
+          bool inside = true;
+          if (P.clip_to_domain) inside = clip_cube(o, d, t_in, t_out);
+          const bool finite = isfinite(o[0]) && isfinite(o[1]) && isfinite(o[2]) && isfinite(d[0]) &&
+                              isfinite(d[1]) && isfinite(d[2]);
+          if (!inside || !finite || !(t_out > t_in)) {
+            job.t_hit[idx] = INFINITY;
+            if (job.iters) job.iters[idx] = 0;
+            continue;
+          }
+          nr = (long long)idx;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            np[a] = o[a] + t_in * d[a];
+            nd[a] = d[a];
+          }
+          ntmax = t_out - t_in;
+          nbase = t_in;
+          break;
+        }
+      }
+      nr = uni(nr);
+      if (nr >= 0) {
+        rid[r] = nr;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          sp[r][a] = uni(np[a]);
+          dv[r][a] = uni(nd[a]);
+        }
+        tmax[r] = uni(ntmax);
+        base[r] = uni(nbase);
+        t[r] = 0.0f;
+        sigma[r] = P.sigma0;
+        it[r] = 0;
+        first[r] = 1;
+      } else {
+        rid[r] = -2;
+      }
+    }
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) any = any || rid[r] >= 0;
+    if (!any) break;   // uniform: every slot drained and no rays left
+
+    // ---- layer 0 for every ray: segment [t, t + sigma] and two passenger points
+    double xc[RPW][4];
+    f4 y[16];
+    float yinf[RPW][4];
+    {
+      const f4* W0 = (const f4*)net.W0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int R = 4 * lane + i;
+        const f4 w = W0[R];
+        const float bb = net.b0[R];
+        y[0][i] = 0.0f;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const int G = 1 + 3 * r;
+          const bool act = rid[r] >= 0;
+          double cc[3];
+          float ax[3], p0[3], p1[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            cc[a] = act ? (double)sp[r][a] + ((double)t[r] + 0.5 * (double)sigma[r]) * (double)dv[r][a] : 0.0;
+            ax[a] = act ? (float)(0.5 * (double)sigma[r] * (double)dv[r][a]) : 0.0f;
+            p0[a] = act ? sp[r][a] + (t[r] + P.delta) * dv[r][a] : 0.0f;
+            p1[a] = act ? sp[r][a] : 0.0f;
+          }
+          xc[r][i] = fma((double)w.z, cc[2], fma((double)w.y, cc[1], fma((double)w.x, cc[0], (double)bb)));
+          y[G][i] = fmaf(w.z, ax[2], fmaf(w.y, ax[1], w.x * ax[0]));
+          y[G + 1][i] = fmaf(w.z, p0[2], fmaf(w.y, p0[1], fmaf(w.x, p0[0], bb)));
+          y[G + 2][i] = fmaf(w.z, p1[2], fmaf(w.y, p1[1], fmaf(w.x, p1[0], bb)));
+          yinf[r][i] = 0.0f;
+        }
+      }
+    }
+    for (int a = 0; a < L - 1; ++a) {
+      activate_packed<ACT>(xc, y, yinf, net.omega0);
+      if (a == L - 2) break;
+      hidden_packed<S>(net, sm, a, xc, y, yinf, lane);
+    }
+    // ---- output layer per ray and the Procedure 2 update (uniform)
+    const f4 wv = *(const f4*)&net.wL[4 * lane];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int G = 1 + 3 * r;
+      double p0 = 0.0;
+      float pinf = 0.0f, pg = 0.0f, q0 = 0.0f, q1 = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        p0 = fma((double)wv[i], xc[r][i], p0);
+        pinf = fmaf(fabsf(wv[i]), yinf[r][i], pinf);
+        pg = fmaf(wv[i], y[G][i], pg);
+        q0 = fmaf(wv[i], y[G + 1][i], q0);
+        q1 = fmaf(wv[i], y[G + 2][i], q1);
+      }
+      p0 = seg_allsum_d<64>(p0);
+      pinf = seg_allsum<64>(pinf);
+      pg = seg_allsum<64>(pg);
+      q0 = seg_allsum<64>(q0) + net.bL;
+      q1 = seg_allsum<64>(q1) + net.bL;
+      if (rid[r] < 0) continue;
+      OutVals o;
+      o.y0 = p0 + (double)net.bL;
+      o.r = (float)((double)fabsf(pg) + (double)pinf);
+      o.err = 0.0f;
+      if (first[r]) {
+        f0[r] = q1;
+        first[r] = 0;
+      }
+      ++it[r];
+      if ((f0[r] > 0.0f) != (q0 > 0.0f)) {
+        if (lane == 0) {
+          job.t_hit[rid[r]] = base[r] + t[r];
+          if (job.iters) job.iters[rid[r]] = it[r];
+        }
+        rid[r] = -1;
+      } else {
+        float lo, hi;
+        enclose(o, false, lo, hi);
+        const bool safe = lo > 0.0f || hi < 0.0f;
+        const float step = safe ? P.safety * sigma[r] : 0.0f;
+        sigma[r] = safe ? sigma[r] * P.eta_plus : sigma[r] * P.eta_minus;
+        t[r] += fmaxf(step, P.delta);
+        if (!(t[r] < tmax[r]) || it[r] >= P.max_iters) {
+          if (lane == 0) {
+            job.t_hit[rid[r]] = INFINITY;
+            if (job.iters) job.iters[rid[r]] = it[r];
+          }
+          rid[r] = -1;
+        }
+      }
+    }
+  }
+}
+
 template <int H>
 static hipError_t launch_rays_h(const NetDev& net, const RayJob& job, hipStream_t stream, int num_cus) {
   using S = Shape<H, 1>;
+  if constexpr (H == 256) {
+    const int64_t nw = (job.n + RPW - 1) / RPW;
+    int64_t blocks = (int64_t)num_cus * 4;
+    if (blocks > nw) blocks = nw;
+    if (blocks < 1) blocks = 1;
+    switch (net.act) {
+      case SPK_ACT_RELU:
+        hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_RELU>), dim3((unsigned)blocks), dim3(64), 0, stream, net,
+                           job);
+        break;
+      case SPK_ACT_ELU:
+        hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_ELU>), dim3((unsigned)blocks), dim3(64), 0, stream, net,
+                           job);
+        break;
+      default:
+        hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_SIN>), dim3((unsigned)blocks), dim3(64), 0, stream, net,
+                           job);
+        break;
+    }
+    return hipGetLastError();
+  }
   const int64_t ngroups = (job.n + S::BPW - 1) / S::BPW;
   int64_t blocks = (int64_t)num_cus * 4;
   if (blocks > ngroups) blocks = ngroups;

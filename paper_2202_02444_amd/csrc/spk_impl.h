@@ -32,6 +32,7 @@ struct NetDev {
   const float* wL;   // [H] output weights
   const uint32_t* Wb;  // (L-2) hidden layers as split BF16 (hi, lo) in 16x16x32 MFMA A-operand order
   float cKs;          // relative rounding bound of a split-BF16 H-term dot product (SPK_PREC_BF16X3)
+  const float* Wr;    // (L-2) hidden layers in 4x4 blocks [k/4][row/4][row%4][k%4]
 };
 
 // Input of a bound launch: which box source feeds the first layer.

@@ -163,12 +163,18 @@ def test_rays_octahedron_closed_form(ctx):
     assert n_hit > 200
 
 
-@pytest.mark.parametrize("netname", ["tiny", "elu64", "blob"])
+@pytest.mark.parametrize("netname", ["tiny", "elu64", "blob", "elu256", "sin256"])
 def test_rays_vs_oracle(ctx, netname):
+    """Width 256 runs the packed kernel (several rays per wavefront); the
+    13 x 13 camera leaves a ragged last group of rays."""
     if netname == "tiny":
         net, side = wl.tiny_net(0), 32
     elif netname == "elu64":
         net, side = wl.he_normal_mlp([3, 64, 64, 64, 1], 41, act="elu", bias=-0.3), 24
+    elif netname == "elu256":
+        net, side = wl.he_normal_mlp([3, 256, 256, 256, 1], 43, act="elu", bias=-0.3), 13
+    elif netname == "sin256":
+        net, side = wl.siren_mlp([3, 256, 256, 256, 1], 44, omega0=30.0), 12
     else:
         net, side = wl.scale_net(1), 16
     o, d = wl.camera_rays(side, side, 7)
@@ -200,6 +206,31 @@ def test_rays_edge_cases(ctx):
         assert np.isfinite(th[i]) == np.isfinite(to[i])
     th2, it2 = _gpu_rays(ctx, net, o[1:2], d[1:2], delta=1e-3, max_iters=3)
     assert it2[0] <= 3
+
+
+def test_rays_edge_cases_packed(ctx):
+    """The same edge cases through the packed width-256 kernel: misses and
+    non-finite rays never occupy a ray slot, and a single ray or an empty
+    batch drains every wavefront."""
+    net = wl.scale_net(1)
+    o = np.array([[5.0, 5.0, 5.0], [0.0, 0.0, 3.0], [0.0, 0.0, 0.0], [np.nan, 0.0, 0.0],
+                  [0.0, 3.0, 0.0], [0.0, 0.0, 0.0], [0.1, 0.2, -3.0]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [1.0, 0.0, 0.0], [1.0, 0.0, 0.0],
+                  [0.0, -1.0, 0.0], [0.0, 0.0, np.inf], [0.0, 0.0, 1.0]], np.float32)
+    th, it = _gpu_rays(ctx, net, o, d, delta=1e-3)
+    assert math.isinf(th[0]) and it[0] == 0
+    assert math.isinf(th[3]) and it[3] == 0
+    assert math.isinf(th[5]) and it[5] == 0
+    live = [1, 2, 4, 6]
+    to, _ = oq.cast_rays(net, o[live].astype(np.float64), d[live].astype(np.float64), delta=1e-3)
+    for j, i in enumerate(live):
+        assert np.isfinite(th[i]) == np.isfinite(to[j]), i
+        if np.isfinite(th[i]):
+            assert abs(th[i] - to[j]) <= 2e-3 + 1e-4, (i, th[i], to[j])
+    th1, it1 = _gpu_rays(ctx, net, o[1:2], d[1:2], delta=1e-3, max_iters=3)
+    assert it1[0] <= 3
+    th0, _ = _gpu_rays(ctx, net, o[:0], d[:0], delta=1e-3)
+    assert th0.shape == (0,)
 
 
 def _l1_ball_distance(x, R):
