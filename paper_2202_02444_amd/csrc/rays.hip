@@ -248,6 +248,78 @@ __device__ __forceinline__ void activate_packed(double (&xc)[RPW][4], f4 (&y)[16
   }
 }
 
+// Generator columns of the tile on MFMA (16x16x4 FP32, one K block of 16 per
+// step) with the row-owner products of every ray interleaved: one k step of
+// 4 per four row tiles, its weights loaded three row tiles before use.
+template <class S>
+__device__ __forceinline__ void packed_pass(PackedRayLds<S>& sm, const f4* Wl, const f4* Wr0, int lane,
+                                            double (&pd)[RPW][4], float (&px)[RPW][4]) {
+  constexpr int MT = S::MT, PF = 4, H = S::H;
+  static_assert(MT % 4 == 0 && MT % PF == 0, "four row tiles per k step");
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      pd[r][i] = 0.0;
+      px[r][i] = 0.0f;
+    }
+  f4 acc[MT];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+  const f4* Wq = Wl + lane;
+  const f4* Wr = Wr0 + 4 * lane;
+  f4 ring[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+  f4 bn = *(const f4*)&sm.base.tile[taddr<S>(0, c, g)];
+#pragma unroll 1
+  for (int t = 0; t < MT; ++t) {
+    const f4 bfr = bn;
+    const int t1 = min(t + 1, MT - 1);
+    bn = *(const f4*)&sm.base.tile[taddr<S>(0, c, 4 * t1 + g)];
+    f4 wv[4];
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      const int k = 16 * t + 4 * (tp >> 2);
+      if ((tp & 3) == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wv[i] = Wr[(size_t)(k / 4) * H + i];
+      }
+      const f4 w = ring[tp % PF];
+      const int qn = min(t * MT + tp + PF, MT * MT - 1);   // past the end: a harmless reload
+      ring[tp % PF] = Wq[(size_t)qn * 64];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[tp] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], bfr[j], acc[tp], 0, 0, 0);
+      if ((tp & 3) == 3) {
+        double wd[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) wd[i][j] = (double)wv[i][j];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const f4 xi = *(const f4*)&sm.vinf[r][k];
+          double xd[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xd[j] = sm.vc[r][k + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              pd[r][i] = fma(wd[i][j], xd[j], pd[r][i]);
+              px[r][i] = fmaf(fabsf(wv[i][j]), xi[j], px[r][i]);
+            }
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) *(f4*)&sm.base.tile[taddr<S>(0, c, 4 * tp + g)] = acc[tp];
+  __syncthreads();
+}
+
 // One H -> H layer for the packed rays.
 template <class S>
 __device__ __forceinline__ void hidden_packed(const NetDev& net, PackedRayLds<S>& sm, int a, double (&xc)[RPW][4],
@@ -262,44 +334,10 @@ __device__ __forceinline__ void hidden_packed(const NetDev& net, PackedRayLds<S>
     for (int i = 0; i < 4; ++i) sm.vc[r][4 * lane + i] = xc[r][i];
   }
   __syncthreads();
-  single_box_pass<S, VA_NONE>(sm.base, (const f4*)net.Wp + (size_t)a * (H * H / 4), 0, lane);
-  // row-owner products: centers (FP64) and |W| xinf of every ray
   double pd[RPW][4];
   float px[RPW][4];
-#pragma unroll
-  for (int r = 0; r < RPW; ++r)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      pd[r][i] = 0.0;
-      px[r][i] = 0.0f;
-    }
-  const f4* Wr = (const f4*)(net.Wr + (size_t)a * H * H) + 4 * lane;
-#pragma unroll 2
-  for (int k = 0; k < H; k += 4) {
-    f4 w[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) w[i] = Wr[(size_t)(k / 4) * H + i];
-    double wd[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) wd[i][j] = (double)w[i][j];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      const f4 xi = *(const f4*)&sm.vinf[r][k];
-      double xd[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xd[j] = sm.vc[r][k + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          pd[r][i] = fma(wd[i][j], xd[j], pd[r][i]);
-          px[r][i] = fmaf(fabsf(w[i][j]), xi[j], px[r][i]);
-        }
-    }
-  }
-  __syncthreads();
+  packed_pass<S>(sm, (const f4*)net.Wp + (size_t)a * (H * H / 4), (const f4*)(net.Wr + (size_t)a * H * H), lane,
+                 pd, px);
 #pragma unroll
   for (int C = 1; C < 16; ++C) y[C] = *(const f4*)&sm.base.tile[taddr<S>(0, C, lane)];
   const f4 bh = *(const f4*)&net.bh[(size_t)a * H + 4 * lane];
