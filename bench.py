@@ -118,10 +118,11 @@ def batched_extra(ctx, dev, policy="truncate", k=K_KEEP):
 
 
 def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, n_sample=2048, steps=2):
-    """Split-BF16 generator products (SPK_PREC_BF16X3) against FP32, both with
-    the rigorous rounding radius: boxes/s on the full batch, and on a sample
-    the bound width relative to the FP64 oracle's exact affine bound (same
-    kept terms), label agreement and sampled soundness."""
+    """Split-BF16 and scaled split-FP16 generator products (SPK_PREC_BF16X3,
+    SPK_PREC_F16X3) against FP32, all with the rigorous rounding radius:
+    boxes/s on the full batch, and on a sample the bound width relative to
+    the FP64 oracle's exact affine bound (same kept terms), label agreement
+    and sampled soundness."""
     import torch
     from oracle import mlp as omlp
     from paper_2202_02444_amd import spk
@@ -129,7 +130,7 @@ def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, n_sample=2048, steps=2):
     lab = torch.empty(n, dtype=torch.uint8, device=dev)
     res = {}
     stream = torch.cuda.current_stream()
-    for prec in ("f32", "bf16x3"):
+    for prec in ("f32", "bf16x3", "f16x3"):
         spk.classify_boxes(ctx, g, tlo, thi, lab, None, None, "truncate", K_KEEP, rigorous=True, prec=prec)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)

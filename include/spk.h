@@ -67,8 +67,18 @@ typedef enum { SPK_AFFINE_FIXED = 0, SPK_AFFINE_TRUNCATE = 1, SPK_AFFINE_FULL = 
  *                  W_lo X_lo and split residuals are bounded a priori and the
  *                  rigorous rounding radius is always applied (as with
  *                  SPK_FLAG_RIGOROUS).  Hidden width 256 only (else
- *                  SPK_E_UNSUPPORTED); single-network bound calls only. */
-typedef enum { SPK_PREC_F32 = 0, SPK_PREC_BF16X3 = 1 } spk_prec;
+ *                  SPK_E_UNSUPPORTED); single-network bound calls only.
+ *  SPK_PREC_F16X3  split FP16 with power-of-two scaling: each hidden layer's W
+ *                  is scaled by 2^sW (max |W| 2^sW in [2^14, 2^15)) and each
+ *                  generator column of X by 2^sc (its max in [2^14, 2^15)),
+ *                  hi = RNE16(v), lo = RNE16((v - hi) 2^11); W_hi X_hi and
+ *                  2^-11 (W_hi X_lo + W_lo X_hi) on the FP16 MFMA (16x16x32)
+ *                  with FP32 accumulation, then unscaled.  The rigorous
+ *                  radius bounds the dropped lo*lo term, the W split
+ *                  residual (measured exactly at network creation), the X
+ *                  split residual, FP16 underflow and the accumulation.
+ *                  Same restrictions as SPK_PREC_BF16X3. */
+typedef enum { SPK_PREC_F32 = 0, SPK_PREC_BF16X3 = 1, SPK_PREC_F16X3 = 2 } spk_prec;
 
 /* uint8 sign classes of Procedure 1. */
 enum { SPK_UNKNOWN = 0, SPK_POSITIVE = 1, SPK_NEGATIVE = 2 };

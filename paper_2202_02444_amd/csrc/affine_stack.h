@@ -445,6 +445,133 @@ __device__ __forceinline__ void single_box_pass_split(LdsState<S>& sm, const f4*
   __syncthreads();
 }
 
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// Split 8 scaled floats into FP16 hi and lo parts (round to nearest even
+// each): hi = RNE16(v), lo = RNE16(v - hi); v - hi is exact in FP32.
+__device__ __forceinline__ void split_f16(const f4& a, const f4& b, h8& hi, h8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float v = i < 4 ? a[i] : b[i - 4];
+    const _Float16 h = (_Float16)v;
+    hi[i] = h;
+    lo[i] = (_Float16)(v - (float)h);
+  }
+}
+
+// Column tile n of the wave's single box (H = 256) with scaled split-FP16
+// generator products.  Each column c of X is scaled by a power of two 2^s_c
+// that puts its max |x| in [2^14, 2^15) (FP16 range, no overflow); W' = W 2^sW
+// is the layer's split copy with unscale factor wsc.  W'_hi X'_hi +
+// W'_hi X'_lo + W'_lo X'_hi run on the 16x16x32 FP16 MFMA with FP32
+// accumulation, and the result is unscaled by the two powers of two.  The
+// FP64 center and the |W| products run first on VALU over the FP32 fragments
+// (first pass only).  Returns the sum of 2^-s_c over the tile's nonzero
+// generator columns (the same value on every lane), which scales the
+// absolute part of the split error.
+template <class S, int VA>
+__device__ __forceinline__ float single_box_pass_f16(LdsState<S>& sm, const f4* Wl, const uint32_t* Whl, float wsc,
+                                                     int n, int lane) {
+  constexpr int MT = S::MT, MT2 = MT / 2, PF = 4;
+  static_assert(S::BPW == 1 && MT % PF == 0, "one box per wave; the ring index repeats every K block");
+  const int g = lane >> 4, c = lane & 15;
+  if (VA != VA_NONE) {
+    // VALU products first, reduced and stored before the MFMA loop so their
+    // partial sums are not live beside the accumulators
+    float px[MT], pe[MT];
+    double pd[MT];
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      px[tp] = 0.0f;
+      pe[tp] = 0.0f;
+      pd[tp] = 0.0;
+    }
+    const f4* Wq = Wl + lane;
+    f4 ring[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+#pragma unroll 1
+    for (int t = 0; t < MT; ++t) {
+      const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
+      f4 ve = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[16 * t + 4 * g];
+      double vd[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
+#pragma unroll
+      for (int tp = 0; tp < MT; ++tp) {
+        const f4 w = ring[tp % PF];
+        const int qn = min(t * MT + tp + PF, MT * MT - 1);
+        ring[tp % PF] = Wq[(size_t)qn * 64];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
+          pd[tp] = fma((double)w[j], vd[j], pd[tp]);
+          if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+  }
+  // this lane's column scale: lanes c, c + 16, c + 32, c + 48 hold the
+  // column's rows 8 g .. 8 g + 7 of every 32-row block
+  float m = 0.0f;
+#pragma unroll 1
+  for (int t2 = 0; t2 < MT2; ++t2) {
+    const f4 b0 = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 8 * t2 + 2 * g)];
+    const f4 b1 = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 8 * t2 + 2 * g + 1)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m = fmaxf(m, fmaxf(fabsf(b0[j]), fabsf(b1[j])));
+  }
+  m = fmaxf(m, __shfl_xor(m, 16, 64));
+  m = fmaxf(m, __shfl_xor(m, 32, 64));
+  const int ex = (int)((__float_as_uint(m) >> 23) & 0xffu) - 127;   // floor(log2 m); -127 for 0
+  const int sh = min(14 - ex, 126);
+  const float sc = __uint_as_float((uint32_t)(sh + 127) << 23);
+  const float isc = __uint_as_float((uint32_t)(127 - sh) << 23);
+  // sum of isc over the generator columns (column 0 of the first tile holds
+  // the center, whose product is not used) with a nonzero entry
+  float ssum = (m > 0.0f && (n > 0 || c > 0)) ? isc : 0.0f;
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) ssum += __shfl_xor(ssum, off, 64);
+  f4 acc[MT];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+  // fragment (t2, tp): two 16-byte vectors (8 hi, 8 lo FP16) per lane
+  const u4v* Bq = (const u4v*)Whl + 2 * lane;
+  u4v rh[PF], rl[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    rh[p] = Bq[(size_t)p * 128];
+    rl[p] = Bq[(size_t)p * 128 + 1];
+  }
+#pragma unroll 1
+  for (int t2 = 0; t2 < MT2; ++t2) {
+    const f4 b0 = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 8 * t2 + 2 * g)];
+    const f4 b1 = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 8 * t2 + 2 * g + 1)];
+    h8 xh, xl;
+    split_f16(b0 * sc, b1 * sc, xh, xl);
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      const h8 ah = __builtin_bit_cast(h8, rh[tp % PF]);
+      const h8 al = __builtin_bit_cast(h8, rl[tp % PF]);
+      const int qn = min(t2 * MT + tp + PF, MT2 * MT - 1);   // past the end: a harmless reload
+      rh[tp % PF] = Bq[(size_t)qn * 128];
+      rl[tp % PF] = Bq[(size_t)qn * 128 + 1];
+      acc[tp] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, xh, acc[tp], 0, 0, 0);
+      acc[tp] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, xl, acc[tp], 0, 0, 0);
+      acc[tp] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, xh, acc[tp], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = (acc[tp] * wsc) * isc;
+  __syncthreads();
+  return ssum;
+}
+
 // Column tile n of every box of the wave (H < 256: several boxes) through one
 // H -> H layer.  This K block's A fragments are held for every output tile
 // (MT is small here) and reused box after box.
@@ -546,7 +673,19 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
 
   // ---- generators on MFMA, center in FP64, |W| xinf and |W| u on VALU ----
   const f4* Wl = (const f4*)net.Wp + (size_t)a * (H * H / 4);
-  if constexpr (PREC == SPK_PREC_BF16X3) {
+  float sc_sum = 0.0f;   // split-FP16: sum of the column unscale factors
+  if constexpr (PREC == SPK_PREC_F16X3) {
+    static_assert(BPW == 1, "scaled split-FP16 products are built for one box per wave");
+    const uint32_t* Whl = net.Wh + (size_t)a * (H * H);   // H*H (hi, lo) pairs of 16-bit values
+    const float wsc = net.wsh[a];
+    if (rigorous)
+      sc_sum = single_box_pass_f16<S, VA_RIGOROUS>(sm, Wl, Whl, wsc, 0, lane);
+    else
+      sc_sum = single_box_pass_f16<S, VA_CENTER>(sm, Wl, Whl, wsc, 0, lane);
+#pragma unroll 1
+    for (int n = 1; n < NT; ++n) sc_sum += single_box_pass_f16<S, VA_NONE>(sm, Wl, Whl, wsc, n, lane);
+    sc_sum *= 1.0f + 3.814697265625e-06f;   // 1 + 2^-18: FP32 sums of at most 32 powers of two
+  } else if constexpr (PREC == SPK_PREC_BF16X3) {
     static_assert(BPW == 1, "split-BF16 products are built for one box per wave");
     const uint32_t* Wbl = net.Wb + (size_t)a * (H * H);   // H*H (hi, lo) pairs of 16-bit values
     if (rigorous)
@@ -590,6 +729,11 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
       for (int C = NS - NPASS; C < NS; ++C) y[C][i] += bh[i];
       yinf[i] = xi[i];
       e[i] = eu[i] * grow + eb[i];
+      // absolute split-FP16 errors, per column c with scale 2^s_c: FP16
+      // underflow of X entries (<= 2^-13 scaled, times |W_hi + W_lo| <=
+      // 2 |W|) and W residuals too small for a normal lo part (D_j times
+      // max |x'| < 2^15); dwt_j bounds 2^-12 sum_k |W_jk| + D_j 2^(15 - sW)
+      if constexpr (PREC == SPK_PREC_F16X3) e[i] = fmaf(net.dwt[(size_t)a * H + 4 * ch + i], sc_sum, e[i]) * kGrow;
     }
   }
   __syncthreads();

@@ -4,6 +4,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <new>
 #include <utility>
 #include <vector>
@@ -50,10 +52,48 @@ float bf16_to_f32(uint16_t h) {
 // in FP32), against sum |w||x|: each operand is w = hi + lo + dw with
 // |lo| <= u_b (1 + u_b) |w| and |dw| <= u_b^2 |w| (u_b = 2^-8, round to
 // nearest), so the dropped lo*lo and the residual terms stay below
-// 3 u_b^2 (1 + 2 u_b) |w||x|; the 3H exact products are then summed in FP32.
+// 3 u_b^2 (1 + 2 u_b) |w||x|; the 3H exact products are then summed in FP32,
+// their magnitudes |hi||hi| + |hi||lo| + |lo||hi| below (1 + 2^-7) |w||x|.
 double split_const(int H) {
   const double ub = ldexp(1.0, -8);
-  return 3.0 * ub * ub * (1.0 + 2.0 * ub) * (1.0 + 1e-6) + dot_const(3 * H, 24);
+  return 3.0 * ub * ub * (1.0 + 2.0 * ub) * (1.0 + 1e-6) + dot_const(3 * H, 24) * (1.0 + ldexp(1.0, -7));
+}
+
+// Binary16 of a finite double with |v| < 65520: round to nearest even on an
+// 11-bit significand; results below the smallest normal (2^-14) are stored as
+// zero, so no FP16 subnormal ever reaches the MFMA.  *val receives the value.
+uint16_t f16_rne_ftz(double v, double* val) {
+  const double a = fabs(v);
+  const uint16_t sign = std::signbit(v) ? 0x8000u : 0u;
+  *val = 0.0;
+  if (a == 0.0) return sign;
+  int e = 0;
+  (void)frexp(a, &e);                          // a in [2^(e-1), 2^e)
+  const double q = ldexp(1.0, e - 11);         // quantum of an 11-bit significand
+  const double r = rint(a / q) * q;            // ties to even (default rounding mode)
+  if (r < ldexp(1.0, -14)) return sign;
+  int e2 = 0;
+  (void)frexp(r, &e2);
+  const int E = e2 - 1;                        // r in [2^E, 2^(E+1))
+  const uint16_t mant = (uint16_t)(ldexp(r, -E) * 1024.0 - 1024.0);
+  *val = std::signbit(v) ? -r : r;
+  return (uint16_t)(sign | (uint16_t)((E + 15) << 10) | mant);
+}
+
+// Relative error bound of a scaled split-FP16 H-term dot product against
+// sum |w'||x'| (scaled operands v' = hi + lo + dv, hi = RNE16(v'),
+// lo = RNE16(v' - hi)): the dropped lo*lo term (<= 2^-22 (1 + 2^-11)^2), the
+// X residual (<= 2^-22 |x'| (1 + 2^-11) plus an absolute part accounted per
+// column), the relative W residual cw (measured exactly over the stored
+// split; weights with a subnormal lo part are accounted absolutely per row),
+// and FP32 accumulation of the 3H exact products.
+double split16_const(int H, double cw) {
+  const double u11 = ldexp(1.0, -11), u22 = ldexp(1.0, -22);
+  // |W_hi + W_lo| <= (1 + 2^-10) |W'| for every weight (cw <= 2^-21; the
+  // absolutely accounted ones have |dw| <= 2^-11 |W'|); the accumulated
+  // magnitudes sum |hi||hi| + |hi||lo| + |lo||hi| stay below (1 + 2^-9) sum |w'||x'|
+  const double rel = u22 * (1.0 + u11) * (1.0 + u11) + u22 * (1.0 + u11) * (1.0 + 2.0 * u11) + cw;
+  return rel * (1.0 + 1e-6) + dot_const(3 * H, 24) * (1.0 + ldexp(1.0, -9));
 }
 
 bool finite_all(const float* p, size_t n) {
@@ -155,6 +195,54 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
           }
         }
   }
+  // scaled split-FP16 copy for SPK_PREC_F16X3, same fragment order as the
+  // BF16 copy: per layer W' = W 2^sW with max |W'| in [2^14, 2^15),
+  // hi = RNE16(W'), lo = RNE16(W' - hi) (no subnormals stored).  The residual
+  // dw = W' - hi - lo is exact in FP64 (all three terms are short); it goes
+  // to the relative bound cw when |dw| <= 2^-21 |W'|, else to the absolute
+  // per-row sum D_j (weights below ~2^-3 in scaled units, whose lo part
+  // underflows).
+  std::vector<uint16_t> Wh(nWb);
+  std::vector<float> wsh((size_t)(L > 2 ? L - 2 : 1), 1.0f), dwt(nbh > 0 ? nbh : 1, 0.0f);
+  std::vector<double> Dj((size_t)H);
+  double cw = 0.0;
+  for (int l = 1; l <= L - 2; ++l) {
+    const float* Wl = W[l];
+    double m = 0.0;
+    for (size_t q = 0; q < (size_t)H * H; ++q) m = fmax(m, fabs((double)Wl[q]));
+    int sW = 0;
+    if (m > 0.0) {
+      int e = 0;
+      (void)frexp(m, &e);
+      sW = std::min(15 - e, 126);
+    }
+    wsh[(size_t)(l - 1)] = (float)ldexp(1.0, -sW);
+    std::fill(Dj.begin(), Dj.end(), 0.0);
+    uint16_t* dst = Wh.data() + (size_t)(l - 1) * H * H * 2;
+    for (int t2 = 0; t2 < MT2; ++t2)
+      for (int tp = 0; tp < MT; ++tp)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int g = lane >> 4, c = lane & 15;
+          uint16_t* o = dst + (((size_t)t2 * MT + tp) * 64 + lane) * 16;
+          for (int i = 0; i < 8; ++i) {
+            const double w = ldexp((double)Wl[(size_t)(16 * tp + c) * H + 32 * t2 + 8 * g + i], sW);
+            double hv = 0.0, lv = 0.0;
+            o[i] = f16_rne_ftz(w, &hv);
+            o[8 + i] = f16_rne_ftz(w - hv, &lv);
+            const double dw = fabs(w - hv - lv);
+            if (dw <= ldexp(fabs(w), -21))
+              cw = fmax(cw, dw / fabs(w));
+            else
+              Dj[(size_t)(16 * tp + c)] += dw;
+          }
+        }
+    // per row: 2^-12 sum_k |W_jk| (X underflow) + D_j 2^(15 - sW) (W residuals)
+    for (int r = 0; r < H; ++r) {
+      double l1 = 0.0;
+      for (int k = 0; k < H; ++k) l1 += fabs((double)Wl[(size_t)r * H + k]);
+      dwt[(size_t)(l - 1) * H + r] = up_f32((ldexp(l1, -12) + Dj[(size_t)r] * ldexp(1.0, 15 - sW)) * (1.0 + 1e-6));
+    }
+  }
   // 4x4 blocks of the hidden layers for row-owner products (packed ray
   // kernel): Wr[l][kb][rb][i][j] = W[4 rb + i][4 kb + j], so lane rb's four
   // rows at one k step are 64 contiguous bytes and a wave's step is one
@@ -175,7 +263,8 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
   const size_t oW0 = 0, ob0 = oW0 + al(nW0 * 4), oWp = ob0 + al(nb0 * 4), obh = oWp + al(nWp * 4 + 4),
                oebh = obh + al(nbh * 4 + 4), owL = oebh + al(nbh * 4 + 4), oWb = owL + al((size_t)H * 4),
-               oWr = oWb + al(nWb * 2 + 4), total = oWr + al(nWp * 4 + 4);
+               oWr = oWb + al(nWb * 2 + 4), oWh = oWr + al(nWp * 4 + 4), owsh = oWh + al(nWb * 2 + 4),
+               odwt = owsh + al(wsh.size() * 4), total = odwt + al(dwt.size() * 4);
   std::vector<unsigned char> img(total, 0);
   memcpy(img.data() + oW0, W0.data(), nW0 * 4);
   memcpy(img.data() + ob0, b0.data(), nb0 * 4);
@@ -187,6 +276,9 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   memcpy(img.data() + owL, wL.data(), (size_t)H * 4);
   if (nWb) memcpy(img.data() + oWb, Wb.data(), nWb * 2);
   if (nWp) memcpy(img.data() + oWr, Wr.data(), nWp * 4);
+  if (nWb) memcpy(img.data() + oWh, Wh.data(), nWb * 2);
+  memcpy(img.data() + owsh, wsh.data(), wsh.size() * 4);
+  memcpy(img.data() + odwt, dwt.data(), dwt.size() * 4);
 
   spk_net* net = new (std::nothrow) spk_net();
   if (net == nullptr) return SPK_E_NOMEM;
@@ -218,6 +310,10 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
   d.Wb = (const uint32_t*)(base + oWb);
   d.cKs = up_f32(split_const(H));
   d.Wr = (const float*)(base + oWr);
+  d.Wh = (const uint32_t*)(base + oWh);
+  d.wsh = (const float*)(base + owsh);
+  d.dwt = (const float*)(base + odwt);
+  d.cKh = up_f32(split16_const(H, cw));
   net->dev_block = blk;
   net->n_linear = n_linear;
   net->width = H;

@@ -67,7 +67,7 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
     int16_t* rec = nullptr;
     if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
     // the next layer's generator products: FP32 or split-BF16 rounding bound
-    const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs : net.cK;
+    const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs : (PREC == SPK_PREC_F16X3 ? net.cKh : net.cK);
     n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec);
     if (a == L - 2) break;
     hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);

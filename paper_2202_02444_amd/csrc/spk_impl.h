@@ -32,6 +32,10 @@ struct NetDev {
   const float* wL;   // [H] output weights
   const uint32_t* Wb;  // (L-2) hidden layers as split BF16 (hi, lo) in 16x16x32 MFMA A-operand order
   float cKs;          // relative rounding bound of a split-BF16 H-term dot product (SPK_PREC_BF16X3)
+  const uint32_t* Wh; // (L-2) hidden layers as scaled split FP16, same fragment order as Wb
+  const float* wsh;   // (L-2) per-layer unscale factors 2^-sW of Wh
+  const float* dwt;   // (L-2) * H : absolute split-FP16 error per unit column scale, per row, rounded up
+  float cKh;          // relative rounding bound of a scaled split-FP16 H-term dot product (SPK_PREC_F16X3)
   const float* Wr;    // (L-2) hidden layers in 4x4 blocks [k/4][row/4][row%4][k%4]
 };
 
@@ -128,7 +132,7 @@ namespace spk {
 // Validation of the bound options shared by every entry point.
 inline spk_status valid_opts(const spk_bound_opts* o) {
   if (o == nullptr) return SPK_E_INVAL;
-  if (o->prec != SPK_PREC_F32 && o->prec != SPK_PREC_BF16X3) return SPK_E_UNSUPPORTED;
+  if (o->prec != SPK_PREC_F32 && o->prec != SPK_PREC_BF16X3 && o->prec != SPK_PREC_F16X3) return SPK_E_UNSUPPORTED;
   if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
   if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
   if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;

@@ -157,7 +157,7 @@ def _ptr(t, dtype=None, shape=None, name="tensor"):
 FLAG_RIGOROUS = 1
 
 
-PREC = {"f32": 0, "bf16x3": 1}
+PREC = {"f32": 0, "bf16x3": 1, "f16x3": 2}
 
 
 def opts(policy="truncate", k=31, rigorous=False, prec="f32"):

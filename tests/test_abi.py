@@ -70,6 +70,12 @@ def test_bound_calls_validate_before_launch():
     full = spk.opts("full", 0)
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(full), 4, FAKE, FAKE, FAKE, None, None,
                                 None) == spk.E_UNSUPPORTED
+    badprec = spk.BoundOpts(1, 31, 3, 0)   # no spk_prec 3
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(badprec), 4, FAKE, FAKE, FAKE, None, None,
+                                None) == spk.E_UNSUPPORTED
+    badflag = spk.BoundOpts(1, 31, 2, 2)   # unknown flag bit
+    assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(badflag), 4, FAKE, FAKE, FAKE, None, None,
+                                None) in (spk.E_INVAL, spk.E_UNSUPPORTED)
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(o), -1, FAKE, FAKE, FAKE, None, None, None) == spk.E_INVAL
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(o), 0, None, None, None, None, None, None) == spk.OK
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(o), 4, None, FAKE, FAKE, None, None, None) == spk.E_INVAL

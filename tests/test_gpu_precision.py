@@ -1,8 +1,9 @@
-"""Split-BF16 generator products (SPK_PREC_BF16X3) against the FP64 oracle and
-the FP32 path: the rigorous radius covers the split arithmetic, so the
-returned bound contains the oracle's exact affine bound (same truncation
-choices, replayed) and every sampled f; the raw bound deviates from the
-oracle by less than the reported radius."""
+"""Split-BF16 and scaled split-FP16 generator products (SPK_PREC_BF16X3,
+SPK_PREC_F16X3) against the FP64 oracle and the FP32 path: the rigorous
+radius covers the split arithmetic, so the returned bound contains the
+oracle's exact affine bound (same truncation choices, replayed) and every
+sampled f; the raw bound deviates from the oracle by less than the reported
+radius."""
 import numpy as np
 import pytest
 
@@ -30,15 +31,16 @@ NETS = {"blob": lambda: wl.scale_net(1),
         "sin3": lambda: wl.siren_mlp([3] + [256] * 3 + [1], 63, 30.0)}
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
 @pytest.mark.parametrize("name", list(NETS))
 @pytest.mark.parametrize("policy,k", [("truncate", 31), ("truncate", 15), ("fixed", 0)])
-def test_split_bf16_encloses_oracle(ctx, name, policy, k):
+def test_split_encloses_oracle(ctx, prec, name, policy, k):
     from paper_2202_02444_amd import spk
     net = NETS[name]()
     g = spk.Net.from_spec(net)
     lo, hi = wl.boxes(384, 64, 1e-4, 0.5)
-    out = gpu_classify(ctx, g, lo, hi, policy, k, want_src=(policy == "truncate"), prec="bf16x3")
-    out2 = gpu_classify(ctx, g, lo, hi, policy, k, prec="bf16x3")
+    out = gpu_classify(ctx, g, lo, hi, policy, k, want_src=(policy == "truncate"), prec=prec)
+    out2 = gpu_classify(ctx, g, lo, hi, policy, k, prec=prec)
     assert np.array_equal(out["lo"], out2["lo"]) and np.array_equal(out["hi"], out2["hi"])
     if policy == "truncate":
         sets = keep_sets_from_src(out["src"], 3, k, 256)
@@ -75,20 +77,63 @@ def test_split_bf16_vs_fp32_rigorous(ctx):
     assert np.max(np.abs(s["radius"] - f["radius"]) / S) < 1e-3
 
 
-def test_split_bf16_unsupported_shapes(ctx):
+def test_split_f16_tighter_than_bf16(ctx):
+    """Scaled split FP16 carries 22 significand bits to BF16's 16: its raw
+    bound is closer to FP32's and its a-priori radius is smaller."""
+    from paper_2202_02444_amd import spk
+    net = wl.he_normal_mlp([3] + [256] * 3 + [1], 66, act="relu")
+    g = spk.Net.from_spec(net)
+    lo, hi = wl.boxes(512, 67, 1e-3, 0.25)
+    h = gpu_classify(ctx, g, lo, hi, "fixed", 0, prec="f16x3")
+    b = gpu_classify(ctx, g, lo, hi, "fixed", 0, prec="bf16x3")
+    f = gpu_classify(ctx, g, lo, hi, "fixed", 0, rigorous=True)
+    S = np.maximum(np.maximum(np.abs(f["lo"]), np.abs(f["hi"])), s_net(net))
+    assert np.all(h["err"] >= f["err"]) and np.all(h["err"] <= b["err"])
+    dh = np.abs(h["radius"] - f["radius"]) / S
+    db = np.abs(b["radius"] - f["radius"]) / S
+    assert np.max(np.abs(h["center"] - f["center"]) / S) < 1e-4
+    assert np.max(dh) < 1e-4 and np.median(dh) < np.median(db)
+
+
+def test_split_f16_extreme_scales(ctx):
+    """Column scaling keeps tiny boxes (generators near 1e-7) and a net with
+    weights scaled by 2^-40 and 2^40 in range: bounds still enclose the oracle
+    and every sampled f."""
+    from paper_2202_02444_amd import spk
+    base = wl.he_normal_mlp([3] + [256] * 3 + [1], 71, act="relu")
+    for sc in (2.0 ** -40, 1.0, 2.0 ** 40):
+        Ws = [w.copy() for w in base.weights]
+        Ws[1] = (Ws[1] * sc).astype(np.float32)
+        Ws[2] = (Ws[2] / sc).astype(np.float32)
+        net = wl.MLPSpec(Ws, [b.copy() for b in base.biases], act="relu", omega0=1.0, name="scaled")
+        g = spk.Net.from_spec(net)
+        for hw in ((1e-7, 1e-6), (1e-3, 0.5)):
+            lo, hi = wl.boxes(256, 72, hw[0], hw[1])
+            out = gpu_classify(ctx, g, lo, hi, "truncate", 15, want_src=True, prec="f16x3")
+            sets = keep_sets_from_src(out["src"], 3, 15, 256)
+            lo_o, hi_o = omlp.bound_boxes(net, lo, hi, "truncate", 15, keep_sets=sets)[2:]
+            S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+            assert np.all(np.isfinite(out["lo"])) and np.all(np.isfinite(out["hi"]))
+            assert np.all(out["lo"] <= lo_o + 1e-12 * S) and np.all(out["hi"] >= hi_o - 1e-12 * S), (sc, hw)
+            bad, _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], np.random.default_rng(73))
+            assert bad == 0
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
+def test_split_unsupported_shapes(ctx, prec):
     import torch
     from paper_2202_02444_amd import spk
     g = spk.Net.from_spec(wl.he_normal_mlp([3, 64, 64, 1], 68))
     lo, hi = wl.boxes(8, 69)
     with pytest.raises(spk.SpkError) as ei:
-        gpu_classify(ctx, g, lo, hi, "truncate", 31, prec="bf16x3")
+        gpu_classify(ctx, g, lo, hi, "truncate", 31, prec=prec)
     assert ei.value.status == spk.E_UNSUPPORTED
     dev = torch.device("cuda")
     items = [{"net": spk.Net.from_spec(wl.he_normal_mlp([3, 256, 256, 1], 70)),
               "box_lo": torch.from_numpy(lo).to(dev), "box_hi": torch.from_numpy(hi).to(dev),
               "label": torch.empty(8, dtype=torch.uint8, device=dev)}]
     import ctypes
-    o = spk.opts("truncate", 31, prec="bf16x3")
+    o = spk.opts("truncate", 31, prec=prec)
     arr = (spk.BatchItem * 1)()
     arr[0] = spk.BatchItem(items[0]["net"].handle.value, 8, items[0]["box_lo"].data_ptr(),
                            items[0]["box_hi"].data_ptr(), items[0]["label"].data_ptr(), None, None)
