@@ -237,8 +237,10 @@ spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params*
  *          upper bound of the distance from q to the surface), +inf when none.
  * The call runs one round per level and waits for each round (it returns with
  * the stream synchronized); it allocates its frontier buffers in device
- * memory and frees them before returning (SPK_E_NOMEM beyond the context's
- * workspace limit).
+ * memory and frees them before returning.  Queries run in chunks of up to
+ * 1024; a chunk whose frontier would exceed the context's workspace limit
+ * (16 GiB when the context has none) is retried in halves, and SPK_E_NOMEM
+ * is returned only when a single query's frontier does not fit.
  */
 spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
                              const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,

@@ -526,7 +526,11 @@ struct CallBuffers {
     *p = nullptr;
     total -= cap;
     cap = 0;
-    if (hipMalloc(p, want) != hipSuccess) return SPK_E_NOMEM;
+    if (hipMalloc(p, want) != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();   // clear it, so that later launch checks do not report it
+      return SPK_E_NOMEM;
+    }
     cap = want;
     total += want;
     bool known = false;
@@ -661,16 +665,23 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
   if (n == 0) return SPK_OK;
   if (q == nullptr || point == nullptr) return SPK_E_INVAL;
 
-  // queries run in chunks so that the frontier memory stays bounded
-  constexpr int64_t kChunk = 1024;
+  // queries run in chunks so that the frontier memory stays bounded; a chunk
+  // whose frontier outgrows the workspace limit is retried in halves (each
+  // chunk starts from the root, so a retry recomputes it in full)
+  int64_t chunk = 1024;
   CpBuffers CB;
-  CB.B.limit = ctx->workspace_limit;
+  CB.B.limit = ctx->workspace_limit ? ctx->workspace_limit : ((size_t)16 << 30);
   CB.B.stream = ctx->stream;
-  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
-    const int64_t cn = (n - c0 < kChunk) ? n - c0 : kChunk;
+  for (int64_t c0 = 0; c0 < n;) {
+    const int64_t cn = (n - c0 < chunk) ? n - c0 : chunk;
     st = closest_chunk(ctx, net, opts, tree, cn, q + 3 * c0, point + 3 * c0, dist ? dist + c0 : nullptr,
                        bound ? bound + c0 : nullptr, CB);
+    if (st == SPK_E_NOMEM && cn > 1) {
+      chunk = (cn + 1) / 2;
+      continue;
+    }
     if (st != SPK_OK) return st;
+    c0 += cn;
   }
   return check_hip(hipStreamSynchronize(ctx->stream));
 }

@@ -337,3 +337,27 @@ def test_closest_point_edge_cases(ctx):
         assert bound[i] >= dstar - 1e-5 and dist[i] <= dstar + math.sqrt(3.0) * 2.0 / 32 + 1e-5
     pt1, _, b1 = _gpu_closest(ctx, net, q[:1], 5)
     assert np.array_equal(b1, bound[:1])
+
+
+def test_closest_point_chunk_halving(ctx):
+    """A workspace limit too small for a 1024-query chunk makes the call
+    retry in halves; the bounds equal those of an unlimited context."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.tiny_net(0)
+    q = wl.points(1500, 43)
+    _, _, b_ref = _gpu_closest(ctx, net, q, 6)
+    small = spk.Context(workspace_bytes=6 << 20)
+    try:
+        _, _, b_small = _gpu_closest(small, net, q, 6)
+    finally:
+        small.close()
+    assert np.array_equal(b_small, b_ref)
+    tiny = spk.Context(workspace_bytes=4096)
+    try:
+        with pytest.raises(spk.SpkError) as ei:
+            _gpu_closest(tiny, net, q[:4], 6)
+        assert ei.value.status == spk.E_NOMEM
+    finally:
+        tiny.close()
+    torch.cuda.synchronize()
