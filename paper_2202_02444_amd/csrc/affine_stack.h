@@ -347,6 +347,95 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
   __syncthreads();
 }
 
+// Both column tiles of the wave's single box (H = 256, 32 term slots) in one
+// sweep over W: every A fragment feeds the MFMAs of both tiles, so W streams
+// from L2 once per layer for the generators instead of once per tile.  The
+// VALU products (FP64 center, |W| xinf, |W| u) run first in a sweep of their
+// own and are stored before the MFMA sweep: their partial sums beside the two
+// accumulator sets would not fit the register file (interleaved, the kernel
+// spills inside the loop and runs 15 % slower).  Each accumulator sees the same
+// product sequence as in single_box_pass, so the results are identical.
+template <class S, int VA>
+__device__ __forceinline__ void single_box_pass2(LdsState<S>& sm, const f4* Wl, int lane) {
+  constexpr int MT = S::MT, PF = 8;
+  static_assert(S::BPW == 1 && S::NT == 2 && MT % PF == 0, "one box per wave, two column tiles");
+  const int g = lane >> 4, c = lane & 15;
+  const f4* Wq = Wl + lane;
+  if (VA != VA_NONE) {
+    float px[MT], pe[MT];
+    double pd[MT];
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      px[tp] = 0.0f;
+      pe[tp] = 0.0f;
+      pd[tp] = 0.0;
+    }
+    f4 ring[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+#pragma unroll 1
+    for (int t = 0; t < MT; ++t) {
+      const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
+      f4 ve = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[16 * t + 4 * g];
+      double vd[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
+#pragma unroll
+      for (int tp = 0; tp < MT; ++tp) {
+        const f4 w = ring[tp % PF];
+        const int qn = min(t * MT + tp + PF, MT * MT - 1);
+        ring[tp % PF] = Wq[(size_t)qn * 64];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
+          pd[tp] = fma((double)w[j], vd[j], pd[tp]);
+          if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+  }
+  f4 acc0[MT], acc1[MT];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    acc0[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+    acc1[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  f4 ring[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+  f4 bn0 = *(const f4*)&sm.tile[taddr<S>(0, c, g)];
+  f4 bn1 = *(const f4*)&sm.tile[taddr<S>(0, 16 + c, g)];
+#pragma unroll 1
+  for (int t = 0; t < MT; ++t) {
+    const f4 b0 = bn0, b1 = bn1;
+    const int t1 = min(t + 1, MT - 1);
+    bn0 = *(const f4*)&sm.tile[taddr<S>(0, c, 4 * t1 + g)];
+    bn1 = *(const f4*)&sm.tile[taddr<S>(0, 16 + c, 4 * t1 + g)];
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      const f4 w = ring[tp % PF];
+      const int qn = min(t * MT + tp + PF, MT * MT - 1);   // past the end: a harmless reload
+      ring[tp % PF] = Wq[(size_t)qn * 64];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc0[tp] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], b0[j], acc0[tp], 0, 0, 0);
+        acc1[tp] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], b1[j], acc1[tp], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    *(f4*)&sm.tile[taddr<S>(0, c, 4 * tp + g)] = acc0[tp];
+    *(f4*)&sm.tile[taddr<S>(0, 16 + c, 4 * tp + g)] = acc1[tp];
+  }
+  __syncthreads();
+}
+
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 
@@ -694,6 +783,11 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
       single_box_pass_split<S, VA_CENTER>(sm, Wl, Wbl, 0, lane);
 #pragma unroll 1
     for (int n = 1; n < NT; ++n) single_box_pass_split<S, VA_NONE>(sm, Wl, Wbl, n, lane);
+  } else if constexpr (BPW == 1 && NT == 2) {
+    if (rigorous)
+      single_box_pass2<S, VA_RIGOROUS>(sm, Wl, lane);
+    else
+      single_box_pass2<S, VA_CENTER>(sm, Wl, lane);
   } else if constexpr (BPW == 1) {
     if (rigorous)
       single_box_pass<S, VA_RIGOROUS>(sm, Wl, 0, lane);
