@@ -232,6 +232,9 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
     }
     if (rec != nullptr) {
       if (ch == 0) {
+        // a rolled loop: unrolled, its 32 per-slot constants would be hoisted
+        // out of the box loop and held (spilled) for the whole kernel
+#pragma unroll 1
         for (int C = 0; C < 32; ++C) {
           const bool fr = (freem >> C) & 1u;
           if (!fr) rec[C] = (C == 0 || C <= k) ? (int16_t)-1 : (int16_t)-2;

@@ -18,12 +18,46 @@
 
 namespace spk {
 
+// Each workgroup takes one contiguous range of box groups, so that the boxes
+// it reads and the lo / hi / label entries it writes share cache lines with
+// its own neighbours only (interleaved groups would spread every output line
+// over several XCDs' L2s and write it back piecemeal).  With one box per
+// wave, the results of each run of 64 boxes are collected in LDS and stored
+// with one coalesced write per array, instead of a 4-byte write per box that
+// the L2 would write back as a partial line again and again while the wave
+// works on the next boxes.
 template <class S, int ACT, int POL, int PREC>
 __global__ __launch_bounds__(64, 1) void bound_kernel(NetDev net, BoundJob job) {
   __shared__ __attribute__((aligned(16))) LdsState<S> sm;
+  __shared__ BoxResult stash[64];
+  const int lane = (int)threadIdx.x;
   const int64_t ngroups = (job.n + S::BPW - 1) / S::BPW;
-  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x)
-    bound_group<S, ACT, POL, PREC>(net, job, sm, grp, (int)threadIdx.x);
+  const int64_t g0 = ngroups * blockIdx.x / gridDim.x, g1 = ngroups * (blockIdx.x + 1) / gridDim.x;
+  if constexpr (S::BPW == 1) {
+    for (int64_t base = g0; base < g1; base += 64) {
+      const int cnt = (int)min((int64_t)64, g1 - base);
+#pragma unroll 1
+      for (int j = 0; j < cnt; ++j) {
+        BoxResult r;
+        bound_group<S, ACT, POL, PREC>(net, job, sm, base + j, lane, &r);
+        if (lane == 0) stash[j] = r;
+      }
+      __syncthreads();
+      if (lane < cnt) {
+        const BoxResult r = stash[lane];
+        const int64_t box = base + lane;
+        if (job.lo) job.lo[box] = r.lo;
+        if (job.hi) job.hi[box] = r.hi;
+        if (job.label) job.label[box] = r.label;
+        if (job.center) job.center[box] = r.center;
+        if (job.radius) job.radius[box] = r.radius;
+        if (job.err) job.err[box] = r.err;
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int64_t grp = g0; grp < g1; ++grp) bound_group<S, ACT, POL, PREC>(net, job, sm, grp, lane);
+  }
 }
 
 template <class S, int ACT, int POL, int PREC>

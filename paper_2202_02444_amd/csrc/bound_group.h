@@ -46,9 +46,18 @@ __device__ __forceinline__ void box_input(const BoundJob& job, int64_t box, bool
   }
 }
 
+// Results of one box (identical in every lane of its segment).
+struct BoxResult {
+  float lo, hi, center, radius, err;
+  uint8_t label;
+};
+
+// With `out` null the box results are written to the job's arrays by the
+// segment's first lane; otherwise (one box per wave) they are returned in
+// *out on every lane and the caller writes them.
 template <class S, int ACT, int POL, int PREC = SPK_PREC_F32>
 __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& job, LdsState<S>& sm, int64_t grp,
-                                            int lane) {
+                                            int lane, BoxResult* out = nullptr) {
   constexpr int NS = S::NS, BPW = S::BPW, SEG = S::SEG;
   const int bo = lane / SEG;
   const int ch = lane % SEG;
@@ -74,16 +83,21 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
   }
   float pass[1];
   const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass);
-  if (valid && ch == 0) {
-    float lo, hi;
-    enclose(o, job.rigorous != 0, lo, hi);
-    if (job.lo) job.lo[box] = lo;
-    if (job.hi) job.hi[box] = hi;
-    if (job.label) job.label[box] = (lo > 0.0f) ? (uint8_t)SPK_POSITIVE
-                                    : (hi < 0.0f) ? (uint8_t)SPK_NEGATIVE : (uint8_t)SPK_UNKNOWN;
-    if (job.center) job.center[box] = (float)o.y0;
-    if (job.radius) job.radius[box] = o.r;
-    if (job.err) job.err[box] = job.rigorous ? o.err : round_up_f(tolerance_margin(o));
+  BoxResult r;
+  enclose(o, job.rigorous != 0, r.lo, r.hi);
+  r.label = (r.lo > 0.0f) ? (uint8_t)SPK_POSITIVE : (r.hi < 0.0f) ? (uint8_t)SPK_NEGATIVE : (uint8_t)SPK_UNKNOWN;
+  r.center = (float)o.y0;
+  r.radius = o.r;
+  r.err = job.rigorous ? o.err : round_up_f(tolerance_margin(o));
+  if (out != nullptr) {
+    *out = r;
+  } else if (valid && ch == 0) {
+    if (job.lo) job.lo[box] = r.lo;
+    if (job.hi) job.hi[box] = r.hi;
+    if (job.label) job.label[box] = r.label;
+    if (job.center) job.center[box] = r.center;
+    if (job.radius) job.radius[box] = r.radius;
+    if (job.err) job.err[box] = r.err;
   }
 }
 
