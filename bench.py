@@ -59,6 +59,42 @@ def measured_traffic():
         return None
 
 
+def rays_extra(ctx, g, dev, side=512, seed=600):
+    """Procedure 2 on one 512x512 view of the 8x256 blob (eye on the sphere of
+    radius 3.5, 60-degree field of view): rays/s, iterations per ray, and the
+    algorithmic rate of the affine-fixed passes.  One iteration on width-256
+    hidden layers is 3 MFMA columns (segment generator, two passenger points)
+    plus the FP64 center and |W| xinf products, 4 products of 2*256*256 FLOP
+    per hidden layer."""
+    import torch
+    import workloads as wl
+    from paper_2202_02444_amd import spk
+    o, d = wl.camera_rays(side, side, seed)
+    to = torch.from_numpy(o).to(dev)
+    td = torch.from_numpy(d).to(dev)
+    th = torch.empty(o.shape[0], device=dev)
+    it = torch.empty(o.shape[0], dtype=torch.int32, device=dev)
+    spk.cast_rays(ctx, g, to, td, th, it)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    spk.cast_rays(ctx, g, to, td, th, it)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    its = it.cpu().numpy().astype(np.int64)
+    n_hidden = 7
+    flop_per_iter = 4 * 2 * 256 * 256 * n_hidden
+    edges = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
+    top = max(edges[-1], int(its.max()) if its.size else 0) + 1
+    hist = np.histogram(its, bins=edges + [top])[0]
+    return {"rays": int(o.shape[0]), "rays_per_s": o.shape[0] / dt, "hits": int(torch.isfinite(th).sum().item()),
+            "iters_mean": float(its.mean()), "iters_p50": float(np.percentile(its, 50)),
+            "iters_p99": float(np.percentile(its, 99)), "iters_max": int(its.max()),
+            "iters_hist_log2_edges": edges, "iters_hist": [int(x) for x in hist],
+            "iterations_per_s": float(its.sum() / dt), "flop_per_iteration": flop_per_iter,
+            "tflops": float(its.sum() * flop_per_iter / dt / 1e12),
+            "frac_fp32_mfma": float(its.sum() * flop_per_iter / dt / PEAK_FP32_MFMA)}
+
+
 def closest_point_extra(ctx, dev, n=4096, max_level=10):
     """Closest point (Section 4.10) for n uniform queries, affine-fixed cells,
     on the tiny 3->32->32->1 ReLU net.  (On the 8x256 blob the affine-fixed
@@ -294,6 +330,8 @@ def main():
     ap.add_argument("--boxes", type=int, default=N_BOXES)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the octree / ray extra measurements")
+    ap.add_argument("--extras", default="octree,rays,closest,batched,precision,serving",
+                    help="comma-separated extra measurements to run")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, one plain device-to-device copy of this many MiB "
@@ -372,38 +410,31 @@ def main():
     }
     if not args.no_extra:
         extra = {}
-        t = time.perf_counter()
-        levels, leaves = spk.build_octree(ctx, g, 10, "truncate", K_KEEP)
-        torch.cuda.synchronize()
-        extra["octree_depth10_s"] = time.perf_counter() - t
-        extra["octree_leaves"] = int(leaves.shape[0])
-        extra["octree_frontier"] = [lv["n"] for lv in levels]
-        progress("octree done")
-        try:
-            o, d = wl.camera_rays(512, 512, 600)
-            to = torch.from_numpy(o).to(dev)
-            td = torch.from_numpy(d).to(dev)
-            th = torch.empty(o.shape[0], device=dev)
-            spk.cast_rays(ctx, g, to, td, th)
-            torch.cuda.synchronize()
+        which = set(args.extras.split(","))
+        if "octree" in which:
             t = time.perf_counter()
-            spk.cast_rays(ctx, g, to, td, th)
+            levels, leaves = spk.build_octree(ctx, g, 10, "truncate", K_KEEP)
             torch.cuda.synchronize()
-            dt = time.perf_counter() - t
-            extra["rays_per_s"] = o.shape[0] / dt
-            extra["ray_hits"] = int(torch.isfinite(th).sum().item())
+            extra["octree_depth10_s"] = time.perf_counter() - t
+            extra["octree_leaves"] = int(leaves.shape[0])
+            extra["octree_frontier"] = [lv["n"] for lv in levels]
+            progress("octree done")
+        if "rays" in which:
+            extra["rays"] = rays_extra(ctx, g, dev)
+            extra["rays_per_s"] = extra["rays"]["rays_per_s"]
             progress("rays done")
-        except spk.SpkError as exc:
-            extra["rays_per_s"] = None
-            extra["rays_note"] = str(exc)
-        extra["closest_point"] = closest_point_extra(ctx, dev)
-        progress("closest point done")
-        extra["batched"] = batched_extra(ctx, dev)
-        progress("batched done")
-        extra["precision"] = precision_extra(ctx, g, net, tlo, thi, lo, hi, dev)
-        progress("precision done")
-        extra["serving"] = serving_extra(dev)
-        progress("serving done")
+        if "closest" in which:
+            extra["closest_point"] = closest_point_extra(ctx, dev)
+            progress("closest point done")
+        if "batched" in which:
+            extra["batched"] = batched_extra(ctx, dev)
+            progress("batched done")
+        if "precision" in which:
+            extra["precision"] = precision_extra(ctx, g, net, tlo, thi, lo, hi, dev)
+            progress("precision done")
+        if "serving" in which:
+            extra["serving"] = serving_extra(dev)
+            progress("serving done")
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, lo, hi, args.cpu_sample)
