@@ -1,0 +1,114 @@
+"""Parity at the measured sizes, in the measured launch configuration: one
+classify launch over the 1,048,576 boxes of the 8x256 blob workload (the boxes
+bench.py times, seed 11), and one 512x512 ray view of the same net (bench.py's
+view, seed 600).  The oracle cannot bound a million boxes in a test, so sampled
+outputs are checked one by one: the GPU's kept sets of the sampled boxes are
+replayed by the oracle, labels must agree outside the ambiguity band, and f
+sampled in every checked box lies inside the bound."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as omlp
+from oracle import queries as oq
+
+from parity import (TOL, default_margin, endpoint_errors, keep_sets_from_src, label_ambiguous, oracle_labels,
+                    s_net, soundness_violations)
+
+pytestmark = pytest.mark.gpu
+
+N_FULL = 1 << 20
+N_SAMPLE = 384
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2202_02444_amd import spk
+    c = spk.Context()
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("policy,k", [("truncate", 31), ("fixed", 0)])
+def test_full_size_boxes_sampled(ctx, policy, k):
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.scale_net(1)
+    g = spk.Net.from_spec(net)
+    lo, hi = wl.boxes(N_FULL, 11, 1e-4, 0.5)
+    dev = torch.device("cuda")
+    tl, th = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
+    lab = torch.empty(N_FULL, dtype=torch.uint8, device=dev)
+    glo = torch.empty(N_FULL, device=dev)
+    ghi = torch.empty(N_FULL, device=dev)
+    cen = torch.empty(N_FULL, device=dev)
+    rad = torch.empty(N_FULL, device=dev)
+    err = torch.empty(N_FULL, device=dev)
+    aux = {"center": cen, "radius": rad, "err": err}
+    src = None
+    if policy == "truncate":
+        src = torch.full((g.n_linear - 1, N_FULL, 32), -3, dtype=torch.int16, device=dev)
+        aux["slot_src"] = src
+    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, policy, k, aux=aux)
+    ctx.sync()
+    # every box got a result
+    assert bool(torch.isfinite(glo).all()) and bool(torch.isfinite(ghi).all())
+    assert bool((glo <= ghi).all())
+    # labels follow the bound everywhere (Procedure 1)
+    lab_from_bound = torch.where(glo > 0, 1, torch.where(ghi < 0, 2, 0)).to(torch.uint8)
+    assert bool((lab == lab_from_bound).all())
+    # sampled boxes: the head, the tail (the last workgroup's range) and a spread
+    rng = np.random.default_rng(17)
+    idx = np.unique(np.concatenate([np.arange(64), np.arange(N_FULL - 64, N_FULL),
+                                    rng.choice(N_FULL, N_SAMPLE - 128, replace=False)]))
+    ti = torch.from_numpy(idx).to(dev)
+    out = {"center": cen[ti].cpu().numpy().astype(np.float64), "radius": rad[ti].cpu().numpy().astype(np.float64),
+           "lo": glo[ti].cpu().numpy().astype(np.float64), "hi": ghi[ti].cpu().numpy().astype(np.float64),
+           "label": lab[ti].cpu().numpy()}
+    slo, shi = lo[idx], hi[idx]
+    if policy == "truncate":
+        sets = keep_sets_from_src(src[:, ti, :].cpu().numpy(), 3, k, 256)
+        lo_o, hi_o = omlp.bound_boxes(net, slo, shi, policy, k, keep_sets=sets)[2:]
+    else:
+        lo_o, hi_o = omlp.bound_boxes(net, slo, shi, policy, k)[2:]
+    S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+    e = endpoint_errors(out["center"], out["radius"], lo_o, hi_o, S)
+    # the documented FP32 ill-conditioning exception of this net: rare boxes
+    # (at most 0.2 % of a sample, here at most one) within 3 TOL
+    assert int((e > TOL).sum()) <= 1, np.sort(e)[-3:]
+    assert e.max() <= 3 * TOL, e.max()
+    amb = label_ambiguous(lo_o, hi_o, S, default_margin(out))
+    lab_o = oracle_labels(lo_o, hi_o)
+    assert np.array_equal(out["label"][~amb], lab_o[~amb])
+    bad, _ = soundness_violations(net, slo, shi, out["lo"], out["hi"], np.random.default_rng(18))
+    assert bad == 0
+
+
+def test_full_size_rays_sampled(ctx):
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.scale_net(1)
+    g = spk.Net.from_spec(net)
+    o, d = wl.camera_rays(512, 512, 600)
+    dev = torch.device("cuda")
+    th = torch.empty(o.shape[0], device=dev)
+    it = torch.empty(o.shape[0], dtype=torch.int32, device=dev)
+    delta = 1e-3
+    spk.cast_rays(ctx, g, torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev), th, it, delta=delta)
+    ctx.sync()
+    th = th.cpu().numpy().astype(np.float64)
+    it = it.cpu().numpy()
+    _, _, inside = oq.clip_to_box(o, d)
+    # rays that miss the cube report no hit and no iteration
+    assert np.all(np.isinf(th[~inside])) and np.all(it[~inside] == 0)
+    rng = np.random.default_rng(19)
+    idx = np.concatenate([rng.choice(np.flatnonzero(inside), 72, replace=False),
+                          rng.choice(np.flatnonzero(~inside), 8, replace=False)])
+    to, _ = oq.cast_rays(net, o[idx].astype(np.float64), d[idx].astype(np.float64), delta=delta)
+    tg = th[idx]
+    agree = np.isfinite(tg) == np.isfinite(to)
+    assert agree.sum() >= idx.size - 2, (idx[~agree], tg[~agree], to[~agree])
+    both = np.isfinite(tg) & np.isfinite(to)
+    assert np.all(np.abs(tg[both] - to[both]) <= 2 * delta + 1e-4)
