@@ -112,3 +112,43 @@ def test_full_size_rays_sampled(ctx):
     assert agree.sum() >= idx.size - 2, (idx[~agree], tg[~agree], to[~agree])
     both = np.isfinite(tg) & np.isfinite(to)
     assert np.all(np.abs(tg[both] - to[both]) <= 2 * delta + 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
+def test_full_size_split_precision_sampled(ctx, prec):
+    """The precision workload at full size (same net and 1M boxes, truncate
+    k = 31, split products with the rigorous radius): sampled boxes contain the
+    oracle's exact bound of the same kept terms, the raw bound lies within the
+    reported radius of it, and sampled f lies inside."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.scale_net(1)
+    g = spk.Net.from_spec(net)
+    lo, hi = wl.boxes(N_FULL, 11, 1e-4, 0.5)
+    dev = torch.device("cuda")
+    tl, th = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
+    lab = torch.empty(N_FULL, dtype=torch.uint8, device=dev)
+    glo = torch.empty(N_FULL, device=dev)
+    ghi = torch.empty(N_FULL, device=dev)
+    cen = torch.empty(N_FULL, device=dev)
+    rad = torch.empty(N_FULL, device=dev)
+    err = torch.empty(N_FULL, device=dev)
+    src = torch.full((g.n_linear - 1, N_FULL, 32), -3, dtype=torch.int16, device=dev)
+    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, "truncate", 31,
+                       aux={"center": cen, "radius": rad, "err": err, "slot_src": src}, prec=prec)
+    ctx.sync()
+    assert bool(torch.isfinite(glo).all()) and bool(torch.isfinite(ghi).all())
+    rng = np.random.default_rng(21)
+    idx = np.unique(np.concatenate([np.arange(32), np.arange(N_FULL - 32, N_FULL),
+                                    rng.choice(N_FULL, 192, replace=False)]))
+    ti = torch.from_numpy(idx).to(dev)
+    g_lo, g_hi = glo[ti].cpu().numpy().astype(np.float64), ghi[ti].cpu().numpy().astype(np.float64)
+    c, r, e = (t[ti].cpu().numpy().astype(np.float64) for t in (cen, rad, err))
+    sets = keep_sets_from_src(src[:, ti, :].cpu().numpy(), 3, 31, 256)
+    lo_o, hi_o = omlp.bound_boxes(net, lo[idx], hi[idx], "truncate", 31, keep_sets=sets)[2:]
+    S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+    assert np.all(g_lo <= lo_o + 1e-12 * S) and np.all(g_hi >= hi_o - 1e-12 * S)
+    tol = e + 1e-6 * S
+    assert np.all(np.abs((c - r) - lo_o) <= tol) and np.all(np.abs((c + r) - hi_o) <= tol)
+    bad, _ = soundness_violations(net, lo[idx], hi[idx], g_lo, g_hi, np.random.default_rng(22))
+    assert bad == 0
