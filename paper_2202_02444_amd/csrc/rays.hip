@@ -250,7 +250,9 @@ __device__ __forceinline__ void activate_packed(double (&xc)[RPW][4], f4 (&y)[16
 
 // Generator columns of the tile on MFMA (16x16x4 FP32, one K block of 16 per
 // step) with the row-owner products of every ray interleaved: one k step of
-// 4 per four row tiles, its weights loaded three row tiles before use.
+// 4 per four row tiles, its weights loaded at the first of them and its rays
+// spread over the other three (2 + 2 + 1 rays), so that every group of four
+// MFMAs has VALU work beside it.
 template <class S>
 __device__ __forceinline__ void packed_pass(PackedRayLds<S>& sm, const f4* Wl, const f4* Wr0, int lane,
                                             double (&pd)[RPW][4], float (&px)[RPW][4]) {
@@ -279,6 +281,7 @@ __device__ __forceinline__ void packed_pass(PackedRayLds<S>& sm, const f4* Wl, c
     const int t1 = min(t + 1, MT - 1);
     bn = *(const f4*)&sm.base.tile[taddr<S>(0, c, 4 * t1 + g)];
     f4 wv[4];
+    double wd[4][4];
 #pragma unroll
     for (int tp = 0; tp < MT; ++tp) {
       const int k = 16 * t + 4 * (tp >> 2);
@@ -291,14 +294,17 @@ __device__ __forceinline__ void packed_pass(PackedRayLds<S>& sm, const f4* Wl, c
       ring[tp % PF] = Wq[(size_t)qn * 64];
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[tp] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[j], bfr[j], acc[tp], 0, 0, 0);
-      if ((tp & 3) == 3) {
-        double wd[4][4];
+      if ((tp & 3) >= 1) {
+        if ((tp & 3) == 1) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) wd[i][j] = (double)wv[i][j];
+            for (int j = 0; j < 4; ++j) wd[i][j] = (double)wv[i][j];
+        }
+        const int rb = (tp & 3) == 1 ? 0 : ((tp & 3) == 2 ? 2 : 4);
+        const int re = (tp & 3) == 3 ? RPW : rb + 2;
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
+        for (int r = rb; r < re; ++r) {
           const f4 xi = *(const f4*)&sm.vinf[r][k];
           double xd[4];
 #pragma unroll
