@@ -338,8 +338,8 @@ def main():
                          "(a known byte count that calibrates the HBM byte counters of a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures one GPU's share of the work; "
+              "sharding over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -48,7 +48,7 @@ typedef enum {
   SPK_E_NOMEM = 2,        /* device or host allocation failed                     */
   SPK_E_NOSPC = 3,        /* an output array is too small; see the call           */
   SPK_E_DEVICE = 4,       /* a HIP runtime call failed                            */
-  SPK_E_UNSUPPORTED = 5,  /* valid request this build does not implement          */
+  SPK_E_UNSUPPORTED = 5,  /* valid request the library does not implement        */
   SPK_E_BUSY = 6          /* object still in use                                  */
 } spk_status;
 

@@ -116,7 +116,7 @@ const char* spk_status_str(spk_status s) {
     case SPK_E_NOMEM: return "out of memory";
     case SPK_E_NOSPC: return "output capacity too small";
     case SPK_E_DEVICE: return "HIP runtime error";
-    case SPK_E_UNSUPPORTED: return "unsupported by this build";
+    case SPK_E_UNSUPPORTED: return "not supported by the library";
     case SPK_E_BUSY: return "object busy";
   }
   return "unknown status";
