@@ -112,18 +112,3 @@ def interval_bound_boxes(net, lo, hi):
             l, u = net.omega0 * l, net.omega0 * u   # omega0 > 0
         l, u = aa.ia_act(net.act, l, u)
     return l[:, 0], u[:, 0]
-
-
-def hidden_ranges_interval(net, lo, hi):
-    """Interval bounds of every hidden pre-activation (for invariants)."""
-    Ws, bs = _w(net)
-    l = np.asarray(lo, dtype=np.float64)
-    u = np.asarray(hi, dtype=np.float64)
-    out = []
-    for i in range(len(Ws) - 1):
-        l, u = aa.ia_linear(l, u, Ws[i], bs[i])
-        if net.act == "sin":
-            l, u = net.omega0 * l, net.omega0 * u
-        out.append((l.copy(), u.copy()))
-        l, u = aa.ia_act(net.act, l, u)
-    return out

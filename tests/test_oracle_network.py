@@ -152,3 +152,96 @@ def test_segment_bound_sound_and_classify():
 def test_classify_strict():
     lab = q.classify(np.array([0.0, 1e-300, -1.0, -1.0]), np.array([1.0, 1.0, 0.0, -1e-300]))
     assert list(lab) == [q.UNKNOWN, q.POSITIVE, q.UNKNOWN, q.NEGATIVE]
+
+
+def _random_rotations(rng, B):
+    """B random proper rotations (QR of Gaussian matrices, sign-fixed)."""
+    Q, R = np.linalg.qr(rng.standard_normal((B, 3, 3)))
+    Q = Q * np.sign(np.diagonal(R, axis1=1, axis2=2))[:, None, :]
+    det = np.linalg.det(Q)
+    Q[det < 0, :, 0] *= -1.0
+    return Q
+
+
+def _positive_linear_net():
+    """The ReLU net of test_exact_on_linear_network: every hidden
+    pre-activation is positive on [-2,2]^3, so it is the linear map J."""
+    net = wl.he_normal_mlp([3, 16, 16, 1], 13, act="relu", bias=0.0)
+    W1 = net.weights[0].astype(np.float64)
+    net.biases[0] = np.full(16, np.abs(W1).sum(1).max() * 2 + 1.0, dtype=np.float32)
+    hmax = np.abs(W1).sum(1).max() * 2 + net.biases[0].astype(np.float64).max()
+    W2 = net.weights[1].astype(np.float64)
+    net.biases[1] = np.full(16, np.abs(W2).sum(1).max() * hmax + 1.0, dtype=np.float32)
+    return net
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_rotated_boxes_exact_on_linear_network(s):
+    """Oriented boxes c + sum_i t_i v_i (t in [-1,1]^s, v_i orthogonal half-axes,
+    Procedure 1's general region): on a network that acts as the linear map J
+    the affine bound is exactly f(c) +- sum_i |J v_i|, and its ends are reached
+    at the box's corners.  The axes are random rotations with unequal
+    half-lengths, so a transposed axis matrix (row i = v_i read as column i)
+    gives a different radius and fails."""
+    rng = np.random.default_rng(70 + s)
+    net = _positive_linear_net()
+    B = 64
+    Q = _random_rotations(rng, B)                      # columns are orthonormal directions
+    h = rng.uniform(0.05, 0.6, (B, 3))
+    axes = np.transpose(Q, (0, 2, 1))[:, :s, :] * h[:, :s, None]   # axes[b, i] = h_i q_i
+    c = rng.uniform(-0.8, 0.8, (B, 3))
+    Ws = [np.asarray(W, dtype=np.float64) for W in net.weights]
+    J = (Ws[2] @ Ws[1] @ Ws[0])[0]
+    fc = mlp.forward(net, c)
+    rad = np.abs(np.einsum("bid,d->bi", axes, J)).sum(axis=1)
+    for policy in ("fixed", "truncate", "full"):
+        ly, hy = mlp.bound_general(net, c, axes, policy, 8)
+        assert np.allclose(ly, fc - rad, rtol=1e-12, atol=1e-10)
+        assert np.allclose(hy, fc + rad, rtol=1e-12, atol=1e-10)
+    # corner brute force: the extremes of a linear map over the box
+    signs = np.array(np.meshgrid(*[[-1.0, 1.0]] * s, indexing="ij")).reshape(s, -1).T
+    for b in range(B):
+        P = c[b] + signs @ axes[b]
+        f = mlp.forward(net, P)
+        assert f.min() == pytest.approx(fc[b] - rad[b], abs=1e-9)
+        assert f.max() == pytest.approx(fc[b] + rad[b], abs=1e-9)
+    # the transposed reading differs on these boxes (guards the pin itself)
+    if s == 3:
+        rad_t = np.abs(np.einsum("bdi,d->bi", axes, J)).sum(axis=1)
+        assert np.max(np.abs(rad_t - rad)) > 1e-3
+
+
+@pytest.mark.parametrize("net_i", [0, 2, 4])
+def test_rotated_boxes_sound_on_nonlinear_nets(net_i):
+    """Soundness by brute force over oriented 3-axis boxes: f at the 27
+    lattice points c + sum_i t_i v_i (t_i in {-1,0,1}) and at random interior
+    points lies inside the bound, for every policy."""
+    net = _tiny_nets()[net_i]
+    rng = np.random.default_rng(80 + net_i)
+    B = 40
+    Q = _random_rotations(rng, B)
+    h = np.exp(rng.uniform(math.log(1e-3), math.log(0.4), (B, 3)))
+    axes = np.transpose(Q, (0, 2, 1)) * h[:, :, None]
+    c = rng.uniform(-1, 1, (B, 3))
+    lat = np.array(np.meshgrid(*[[-1.0, 0.0, 1.0]] * 3, indexing="ij")).reshape(3, -1).T
+    for policy, k in (("fixed", 3), ("truncate", 5), ("full", 3)):
+        ly, hy = mlp.bound_general(net, c, axes, policy, k)
+        for b in range(B):
+            T = np.concatenate([lat, rng.uniform(-1, 1, (100, 3))])
+            f = mlp.forward(net, c[b] + T @ axes[b])
+            tol = 1e-10 * max(1.0, np.abs(f).max())
+            assert f.min() >= ly[b] - tol and f.max() <= hy[b] + tol, (policy, b)
+
+
+def test_rotated_box_equals_aabb_when_axes_are_diagonal():
+    """With axes diag(h) the general-box form is the AABB form exactly."""
+    net = _tiny_nets()[1]
+    rng = np.random.default_rng(90)
+    B = 30
+    c = rng.uniform(-1, 1, (B, 3))
+    h = np.exp(rng.uniform(math.log(1e-3), math.log(0.4), (B, 3)))
+    axes = np.zeros((B, 3, 3))
+    axes[:, [0, 1, 2], [0, 1, 2]] = h
+    ly, hy = mlp.bound_general(net, c, axes, "truncate", 7)
+    _, _, la, ha = mlp.bound_boxes(net, c - h, c + h, "truncate", 7)
+    assert np.allclose(ly, la, rtol=1e-13, atol=1e-13) and np.allclose(hy, ha, rtol=1e-13, atol=1e-13)
