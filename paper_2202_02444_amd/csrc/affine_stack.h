@@ -59,10 +59,15 @@ __device__ __forceinline__ float round_up_f(double v) {
 // radius.  On exit xc/y/yinf/e hold the post-activation form and u = e + cK r
 // + cD |x0| is the vector the next layer's rounding-error product |W| u needs.
 // Returns the new number of occupied generator slots.
+//
+// With `sent` non-null (first activation of a bound pass, truncate), every
+// kept new term placed in a slot C >= 4 is also recorded as the single entry
+// of its column: sent[C] = its value gamma_j and sent[S::NS + C] = its row j
+// (as an int), for the first hidden layer's row-owner products.
 template <class S, int ACT, int POL, int NPASS>
 __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
                                         float (&u)[4], int n_occ, int k, float cK, float cD, float omega0, int lane,
-                                        int16_t* rec) {
+                                        int16_t* rec, float* sent = nullptr) {
   static_assert(NPASS == 0 || POL == SPK_AFFINE_FIXED, "passengers ride along affine-fixed passes only");
   constexpr int NG = S::NS - NPASS;   // slots 1..NG-1 are generators
   float gam[4], rnext[4];
@@ -229,6 +234,15 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
       }
       zi += keepnew[i] ? 0.0 : (double)gam[i];
       yinf[i] = (float)zi;
+    }
+    if (sent != nullptr) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (slot[i] >= 4) {
+          sent[slot[i]] = gam[i];
+          ((int*)sent)[S::NS + slot[i]] = 4 * ch + i;
+        }
+      }
     }
     if (rec != nullptr) {
       if (ch == 0) {
@@ -834,6 +848,125 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
     }
   }
   __syncthreads();
+}
+
+// LDS scratch of the first hidden layer inside the (then unused) tile: per
+// box the three dense columns [3][H], after them per box the single-entry
+// table written by the first activation (NS values, then NS row indices).
+template <class S>
+__device__ __forceinline__ float* first_layer_dense(LdsState<S>& sm, int bo) {
+  return sm.tile + bo * (3 * S::H);
+}
+template <class S>
+__device__ __forceinline__ float* first_layer_sent(LdsState<S>& sm, int bo) {
+  static_assert(S::BPW * (3 * S::H + 2 * S::NS) <= S::TILE, "first-layer scratch must fit the tile");
+  return sm.tile + S::BPW * (3 * S::H) + bo * (2 * S::NS);
+}
+
+// The first H -> H layer (Table 2 matrix multiplication) in owner layout,
+// without the matrix core.  Entering it, the generator slots hold the s <= 3
+// input-axis columns (slots 1..3, dense: kept old terms keep their slots) and,
+// in slots 4..klast, new terms of the first truncation (Section 3.3), each a
+// single entry gamma_j on row j.  The center and the dense columns are
+// multiplied by W in FP64 and rounded once: at this layer the FP32 rounding of
+// the input-axis columns is what the chord slopes of narrow straddling neurons
+// amplify most in the later layers.  A single-entry column is the scaled
+// weight column W[:, j] gamma_j (one FP32 rounding, the value any FP32
+// summation order gives).  |W| xinf and, in the rigorous mode, |W| u run in
+// FP32.  Lane ch owns rows 4ch..4ch+3 of its box and streams W from the
+// 4x4-blocked copy (one coalesced 64-byte row block per lane and k block); the
+// box's vectors are LDS broadcasts.  The rounding-error radius keeps the
+// a-priori bound of the next activation's constant cK, which covers this
+// evaluation too.
+template <class S, bool RIG>
+__device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S>& sm, double (&xc)[4],
+                                                   f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
+                                                   const float (&u)[4], int lane, int klast) {
+  constexpr int H = S::H, NS = S::NS, SEG = S::SEG;
+  const int bo = lane / SEG;
+  const int ch = lane % SEG;
+  float* dense = first_layer_dense<S>(sm, bo);
+  const float* sent = first_layer_sent<S>(sm, bo);
+  // ---- owner layout -> LDS (the box's vectors and dense columns) ----
+#pragma unroll
+  for (int c = 0; c < 3; ++c) *(f4*)&dense[c * H + 4 * ch] = y[c + 1];
+  {
+    f4 v1 = {yinf[0], yinf[1], yinf[2], yinf[3]};
+    *(f4*)&sm.vinf[4 * lane] = v1;
+    if (RIG) {
+      f4 v2 = {u[0], u[1], u[2], u[3]};
+      *(f4*)&sm.vu[4 * lane] = v2;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sm.vc[4 * lane + i] = xc[i];
+  }
+  __syncthreads();
+  const double* vc = sm.vc + bo * H;
+  const float* vi = sm.vinf + bo * H;
+  const float* vu = sm.vu + bo * H;
+  const f4* Wr = (const f4*)net.Wr + 4 * ch;   // hidden layer 0
+  double a0[4], a1[4], a2[4], a3[4];
+  float px[4], pe[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    a0[i] = 0.0; a1[i] = 0.0; a2[i] = 0.0; a3[i] = 0.0;
+    px[i] = 0.0f; pe[i] = 0.0f;
+  }
+#pragma unroll 2
+  for (int kb = 0; kb < H / 4; ++kb) {
+    f4 w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = Wr[(size_t)kb * H + i];
+    const f4 d1 = *(const f4*)&dense[4 * kb];
+    const f4 d2 = *(const f4*)&dense[H + 4 * kb];
+    const f4 d3 = *(const f4*)&dense[2 * H + 4 * kb];
+    const f4 xi = *(const f4*)&vi[4 * kb];
+    f4 uu = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (RIG) uu = *(const f4*)&vu[4 * kb];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double x0 = vc[4 * kb + j];
+      const double x1 = (double)d1[j], x2 = (double)d2[j], x3 = (double)d3[j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double wd = (double)w[i][j];
+        a0[i] = fma(wd, x0, a0[i]);
+        a1[i] = fma(wd, x1, a1[i]);
+        a2[i] = fma(wd, x2, a2[i]);
+        a3[i] = fma(wd, x3, a3[i]);
+        px[i] = fmaf(fabsf(w[i][j]), xi[j], px[i]);
+        if (RIG) pe[i] = fmaf(fabsf(w[i][j]), uu[j], pe[i]);
+      }
+    }
+  }
+  // ---- single-entry columns: y[C] = W[:, j] gamma_j; slots past klast are
+  // empty (assigned here so that no slot stays live across the loop above) ----
+#pragma unroll
+  for (int C = 4; C < NS; ++C) {
+    f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (C <= klast) {
+      const float g = sent[C];
+      const int j = ((const int*)sent)[NS + C];
+      const float* wc = net.Wr + ((size_t)(j >> 2) * H + 4 * ch) * 4 + (j & 3);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = wc[4 * i] * g;
+    }
+    y[C] = v;
+  }
+  __syncthreads();
+  const f4 bh = *(const f4*)&net.bh[4 * ch];
+  const f4 eb = *(const f4*)&net.ebh[4 * ch];
+  const float grow = 1.0f + 2.0f * net.cK;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    xc[i] = a0[i] + (double)bh[i];
+    y[0][i] = (float)xc[i];
+    y[1][i] = (float)a1[i];
+    y[2][i] = (float)a2[i];
+    y[3][i] = (float)a3[i];
+    yinf[i] = px[i];
+    e[i] = pe[i] * grow + eb[i];
+  }
 }
 
 struct OutVals {

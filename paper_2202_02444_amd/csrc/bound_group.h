@@ -72,14 +72,40 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
   float yinf[4], e[4], u[4];
   layer0_affine<S, 0>(net, ch, cc, ax, ein, pts, xc, y, yinf, e);
   int n_occ = job.s;
-  for (int a = 0; a < L - 1; ++a) {
-    int16_t* rec = nullptr;
-    if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
-    // the next layer's generator products: FP32 or split-BF16 rounding bound
-    const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs : (PREC == SPK_PREC_F16X3 ? net.cKh : net.cK);
-    n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec);
-    if (a == L - 2) break;
-    hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
+  // the next layer's generator products: FP32 or split-BF16 rounding bound
+  const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs : (PREC == SPK_PREC_F16X3 ? net.cKh : net.cK);
+  if constexpr (S::BPW == 1) {
+    {
+      // first activation; with a hidden H -> H layer after it, that layer's
+      // generator columns are the input axes and single entries: row-owner
+      // products, the dense ones in FP64
+      int16_t* rec = (job.slot_src != nullptr && valid) ? job.slot_src + (size_t)box * 32 : nullptr;
+      float* sent = POL == SPK_AFFINE_TRUNCATE ? first_layer_sent<S>(sm, bo) : nullptr;
+      n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec, sent);
+    }
+    if (L > 2) {
+      const int klast = POL == SPK_AFFINE_TRUNCATE ? job.k : 3;
+      if (job.rigorous)
+        first_hidden_layer<S, true>(net, sm, xc, y, yinf, e, u, lane, klast);
+      else
+        first_hidden_layer<S, false>(net, sm, xc, y, yinf, e, u, lane, klast);
+      for (int a = 1; a < L - 1; ++a) {
+        int16_t* rec = nullptr;
+        if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
+        n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec);
+        if (a == L - 2) break;
+        hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
+      }
+    }
+  } else {
+    // several boxes per wave (H < 256): every hidden layer on the MFMA
+    for (int a = 0; a < L - 1; ++a) {
+      int16_t* rec = nullptr;
+      if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
+      n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec);
+      if (a == L - 2) break;
+      hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
+    }
   }
   float pass[1];
   const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass);

@@ -107,22 +107,17 @@ def test_activation_matrix(ctx, act, H, depth, policy, k):
 
 
 def test_scale_net_sample(ctx):
-    """The 3 -> 256x8 -> 1 closed-blob net, truncate k = 31 and fixed.
-
-    Every box within TOL, except for rare boxes whose bound is ill-conditioned
-    in FP32: the ReLU chord parameters of narrow straddling neurons in the
-    first layers amplify the unit roundoff of the FP32 generators about
-    100-fold (box 94 of this sample reaches 1.2e-5 with FP32 generators
-    computed on the CPU in BLAS order, so no FP32 evaluation order meets TOL
-    there).  Such boxes may make up at most 0.2 % of the sample and stay within
-    3 TOL."""
+    """The 3 -> 256x8 -> 1 closed-blob net, truncate k = 31 and fixed: every
+    box within TOL (the first hidden layer's input-axis columns are
+    accumulated in FP64; in FP32 their rounding, amplified by the chord slopes
+    of narrow straddling neurons, moved rare boxes past TOL)."""
     net = wl.scale_net(1)
     lo, hi = wl.boxes(1024, 11, 1e-4, 0.5)
     for policy, k in (("truncate", 31), ("fixed", 0)):
         r = _run(ctx, net, lo, hi, policy, k, sound_rng=np.random.default_rng(4))
         key = "replay" if policy == "truncate" else "free"
-        assert np.mean(r[key] > TOL) <= 2e-3, (policy, np.mean(r[key] > TOL))
-        assert r[key].max() <= 3 * TOL, (policy, r[key].max())
+        print(policy, "max endpoint error %.3e" % r[key].max())
+        assert r[key].max() <= TOL, (policy, np.sort(r[key])[-3:])
         assert r["violations"] == 0
 
 

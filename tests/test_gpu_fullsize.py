@@ -75,10 +75,8 @@ def test_full_size_boxes_sampled(ctx, policy, k):
         lo_o, hi_o = omlp.bound_boxes(net, slo, shi, policy, k)[2:]
     S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
     e = endpoint_errors(out["center"], out["radius"], lo_o, hi_o, S)
-    # the documented FP32 ill-conditioning exception of this net: rare boxes
-    # (at most 0.2 % of a sample, here at most one) within 3 TOL
-    assert int((e > TOL).sum()) <= 1, np.sort(e)[-3:]
-    assert e.max() <= 3 * TOL, e.max()
+    print("max endpoint error %.3e (TOL %.0e)" % (e.max(), TOL))
+    assert e.max() <= TOL, np.sort(e)[-3:]
     amb = label_ambiguous(lo_o, hi_o, S, default_margin(out))
     lab_o = oracle_labels(lo_o, hi_o)
     assert np.array_equal(out["label"][~amb], lab_o[~amb])
