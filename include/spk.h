@@ -49,7 +49,8 @@ typedef enum {
   SPK_E_NOSPC = 3,        /* an output array is too small; see the call           */
   SPK_E_DEVICE = 4,       /* a HIP runtime call failed                            */
   SPK_E_UNSUPPORTED = 5,  /* valid request the library does not implement        */
-  SPK_E_BUSY = 6          /* object still in use                                  */
+  SPK_E_BUSY = 6,         /* object still in use                                  */
+  SPK_E_LIMIT = 7         /* request exceeds a fixed capacity of the library       */
 } spk_status;
 
 /* Activations (Table 3).  SPK_ACT_SIN is sin(omega0 * z) (SIREN convention). */
@@ -200,6 +201,25 @@ spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bo
                                   const spk_tree_params* tree, int32_t level, const uint64_t* cells,
                                   int64_t n, uint64_t* children, int64_t cap_children, uint64_t* leaves,
                                   int64_t cap_leaves, int64_t* counts);
+
+/*
+ * spk_subdivide_frontier_noalloc: spk_subdivide_frontier for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors, but the per-cell labels of the round live in a fixed, library-owned
+ * device array of SPK_NOALLOC_MAX_CELLS bytes (one copy per GPU, held until
+ * the process ends) instead of the context's workspace, and the call makes no
+ * allocation (no hipMalloc / hipFree).
+ *   n > SPK_NOALLOC_MAX_CELLS returns SPK_E_LIMIT before any HIP call.
+ * Every call on one GPU shares that array: calls that overlap on a GPU (from
+ * several contexts or streams) race and must be serialised by the caller.
+ * The array needs no clearing: each call writes every label it reads.
+ */
+#define SPK_NOALLOC_MAX_CELLS 16777216
+spk_status spk_subdivide_frontier_noalloc(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                                          const spk_tree_params* tree, int32_t level, const uint64_t* cells,
+                                          int64_t n, uint64_t* children, int64_t cap_children, uint64_t* leaves,
+                                          int64_t cap_leaves, int64_t* counts);
 
 /* CastRay parameters (Procedure 2; Section 4.1 delta; Appendix B safety). */
 typedef struct {

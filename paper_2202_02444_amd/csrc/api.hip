@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -107,6 +108,36 @@ spk_status check_hip(hipError_t e) { return e == hipSuccess ? SPK_OK : SPK_E_DEV
 
 }  // namespace
 
+// Fixed scratch of spk_subdivide_frontier_noalloc: the per-cell labels of one
+// frontier round (one byte per cell).  Every GPU the library runs on holds its
+// own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for that device (the array's name is not
+// a device address on the host).
+static __device__ __align__(256) uint8_t scratch[SPK_NOALLOC_MAX_CELLS];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with that
+// device current (the caller's current device is restored).
+static spk_status noalloc_scratch(int device, void** p) {
+  if (device < 0 || device >= kMaxDevices) return SPK_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return SPK_E_DEVICE;
+    if (cur != device && hipSetDevice(device) != hipSuccess) return SPK_E_DEVICE;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || ptr == nullptr) return SPK_E_DEVICE;
+    g_scratch_ptr[device] = ptr;
+  }
+  *p = g_scratch_ptr[device];
+  return SPK_OK;
+}
+
 extern "C" {
 
 const char* spk_status_str(spk_status s) {
@@ -118,6 +149,7 @@ const char* spk_status_str(spk_status s) {
     case SPK_E_DEVICE: return "HIP runtime error";
     case SPK_E_UNSUPPORTED: return "not supported by the library";
     case SPK_E_BUSY: return "object busy";
+    case SPK_E_LIMIT: return "request exceeds a fixed capacity of the library";
   }
   return "unknown status";
 }
@@ -441,26 +473,12 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
   return launch_bound(net, job, ctx->stream, ctx->num_cus);
 }
 
-spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+// One frontier round given the per-cell label buffer `labels` (n bytes of
+// device memory the call may overwrite).
+static spk_status subdivide_round(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
                                   const spk_tree_params* tree, int32_t level, const uint64_t* cells, int64_t n,
                                   uint64_t* children, int64_t cap_children, uint64_t* leaves, int64_t cap_leaves,
-                                  int64_t* counts) {
-  if (ctx == nullptr || net == nullptr || tree == nullptr || counts == nullptr) return SPK_E_INVAL;
-  spk_status st = valid_opts(opts);
-  if (st != SPK_OK) return st;
-  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
-  if (tree->max_level < 0 || tree->max_level > 20 || level < 0 || level > tree->max_level) return SPK_E_INVAL;
-  for (int d = 0; d < 3; ++d)
-    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
-      return SPK_E_INVAL;
-  if (n < 0 || cap_children < 0 || cap_leaves < 0) return SPK_E_INVAL;
-  if (n > 0 && cells == nullptr) return SPK_E_INVAL;
-  if ((cap_children > 0 && children == nullptr) || (cap_leaves > 0 && leaves == nullptr)) return SPK_E_INVAL;
-  void* scratch = nullptr;
-  if (n > 0) {
-    st = ctx_scratch(ctx, (size_t)n, &scratch);
-    if (st != SPK_OK) return st;
-  }
+                                  int64_t* counts, uint8_t* labels) {
   BoundJob job = {};
   job.n = n;
   job.mode = IN_CELL;
@@ -475,13 +493,62 @@ spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bo
     job.dom_lo[d] = tree->dom_lo[d];
     job.dom_hi[d] = tree->dom_hi[d];
   }
-  job.label = (uint8_t*)scratch;
+  job.label = labels;
   if (n > 0) {
-    st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+    spk_status st = launch_bound(net, job, ctx->stream, ctx->num_cus);
     if (st != SPK_OK) return st;
   }
-  return launch_compact((const uint8_t*)scratch, cells, n, level == tree->max_level, children, cap_children, leaves,
-                        cap_leaves, counts, ctx->stream, ctx->num_cus);
+  return launch_compact(labels, cells, n, level == tree->max_level, children, cap_children, leaves, cap_leaves,
+                        counts, ctx->stream, ctx->num_cus);
+}
+
+static spk_status check_subdivide_args(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                                       const spk_tree_params* tree, int32_t level, const uint64_t* cells, int64_t n,
+                                       const uint64_t* children, int64_t cap_children, const uint64_t* leaves,
+                                       int64_t cap_leaves, const int64_t* counts) {
+  if (ctx == nullptr || net == nullptr || tree == nullptr || counts == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
+  if (st != SPK_OK) return st;
+  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
+  if (tree->max_level < 0 || tree->max_level > 20 || level < 0 || level > tree->max_level) return SPK_E_INVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
+      return SPK_E_INVAL;
+  if (n < 0 || cap_children < 0 || cap_leaves < 0) return SPK_E_INVAL;
+  if (n > 0 && cells == nullptr) return SPK_E_INVAL;
+  if ((cap_children > 0 && children == nullptr) || (cap_leaves > 0 && leaves == nullptr)) return SPK_E_INVAL;
+  return SPK_OK;
+}
+
+spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                                  const spk_tree_params* tree, int32_t level, const uint64_t* cells, int64_t n,
+                                  uint64_t* children, int64_t cap_children, uint64_t* leaves, int64_t cap_leaves,
+                                  int64_t* counts) {
+  spk_status st = check_subdivide_args(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves,
+                                       cap_leaves, counts);
+  if (st != SPK_OK) return st;
+  void* labels = nullptr;
+  if (n > 0) {
+    st = ctx_scratch(ctx, (size_t)n, &labels);
+    if (st != SPK_OK) return st;
+  }
+  return subdivide_round(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves, cap_leaves, counts,
+                         (uint8_t*)labels);
+}
+
+spk_status spk_subdivide_frontier_noalloc(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
+                                          const spk_tree_params* tree, int32_t level, const uint64_t* cells,
+                                          int64_t n, uint64_t* children, int64_t cap_children, uint64_t* leaves,
+                                          int64_t cap_leaves, int64_t* counts) {
+  spk_status st = check_subdivide_args(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves,
+                                       cap_leaves, counts);
+  if (st != SPK_OK) return st;
+  if (n > (int64_t)SPK_NOALLOC_MAX_CELLS) return SPK_E_LIMIT;
+  void* labels = nullptr;
+  st = noalloc_scratch(ctx->device, &labels);
+  if (st != SPK_OK) return st;
+  return subdivide_round(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves, cap_leaves, counts,
+                         (uint8_t*)labels);
 }
 
 spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params* params, int64_t n,

@@ -15,14 +15,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspk.so")
 
-OK, E_INVAL, E_NOMEM, E_NOSPC, E_DEVICE, E_UNSUPPORTED, E_BUSY = range(7)
+OK, E_INVAL, E_NOMEM, E_NOSPC, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_LIMIT = range(8)
+NOALLOC_MAX_CELLS = 16777216
 ACT = {"relu": 0, "elu": 1, "sin": 2}
 POLICY = {"fixed": 0, "truncate": 1, "full": 2}
 UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
-           "spk_subdivide_frontier", "spk_cast_rays", "spk_eval_points", "spk_closest_point",
+           "spk_subdivide_frontier", "spk_subdivide_frontier_noalloc", "spk_cast_rays", "spk_eval_points", "spk_closest_point",
            "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
            "spk_batch_destroy", "spk_server_create", "spk_server_submit", "spk_server_poll",
            "spk_server_pending", "spk_server_destroy")
@@ -104,6 +105,8 @@ def lib():
         L.spk_classify_boxes.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, vp, vp, vp, vp, vp,
                                          ctypes.POINTER(BoundAux)]
         L.spk_subdivide_frontier.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
+                                             i64, vp, i64, vp, i64, vp]
+        L.spk_subdivide_frontier_noalloc.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
         L.spk_eval_points.argtypes = [vp, vp, i64, vp, vp]
@@ -263,19 +266,22 @@ def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=Non
 
 
 def subdivide_frontier(ctx, net, level, cells, children, leaves, counts, max_level, policy="truncate", k=31,
-                       dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8):
+                       dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8, noalloc=False):
+    """One round of Procedure 3 (spk_subdivide_frontier, or with
+    noalloc=True spk_subdivide_frontier_noalloc)."""
     import torch
     tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), int(arity))
     o = opts(policy, k)
     n = cells.shape[0]
     capc = children.shape[0] if children is not None else 0
     capl = leaves.shape[0] if leaves is not None else 0
-    st = lib().spk_subdivide_frontier(ctx.handle, net.handle, ctypes.byref(o), ctypes.byref(tp), int(level),
-                                      _ptr(cells, torch.int64, (n,), "cells"), n,
-                                      _ptr(children, torch.int64, None, "children"), capc,
-                                      _ptr(leaves, torch.int64, None, "leaves"), capl,
-                                      _ptr(counts, torch.int64, (4,), "counts"))
-    _check(st, "spk_subdivide_frontier")
+    name = "spk_subdivide_frontier_noalloc" if noalloc else "spk_subdivide_frontier"
+    st = getattr(lib(), name)(ctx.handle, net.handle, ctypes.byref(o), ctypes.byref(tp), int(level),
+                              _ptr(cells, torch.int64, (n,), "cells"), n,
+                              _ptr(children, torch.int64, None, "children"), capc,
+                              _ptr(leaves, torch.int64, None, "leaves"), capl,
+                              _ptr(counts, torch.int64, (4,), "counts"))
+    _check(st, name)
 
 
 def ray_params(delta=1e-3, t_max=10.0, sigma0=None, eta_minus=0.5, eta_plus=1.5, safety=0.98, max_iters=100000,

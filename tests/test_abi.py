@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     L = spk.lib()
-    for s in range(7):
+    for s in range(8):
         assert L.spk_status_str(s)
     assert b"gfx950" in L.spk_version()
 
@@ -105,6 +105,16 @@ def test_tree_and_ray_validation():
                                     cnt) == spk.E_INVAL      # empty domain
     assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 0, FAKE, 1, None, 8, None, 0,
                                     cnt) == spk.E_INVAL      # capacity without buffer
+    # the non-allocating variant validates the same way and rejects frontiers
+    # beyond its fixed scratch before any HIP call
+    assert L.spk_subdivide_frontier_noalloc(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 7, FAKE, 1, FAKE, 8,
+                                            None, 0, cnt) == spk.E_INVAL
+    hdr = open(os.path.join(ROOT, "include", "spk.h")).read()
+    assert int(re.search(r"#define SPK_NOALLOC_MAX_CELLS (\d+)", hdr).group(1)) == spk.NOALLOC_MAX_CELLS
+    big = spk.NOALLOC_MAX_CELLS + 1
+    assert L.spk_subdivide_frontier_noalloc(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 0, FAKE, big, FAKE,
+                                            8 * big, None, 0, cnt) == spk.E_LIMIT
+    assert b"fixed capacity" in L.spk_status_str(spk.E_LIMIT)
     rp = spk.ray_params()
     assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp), -1, FAKE, FAKE, FAKE, None) == spk.E_INVAL
     assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp), 0, None, None, None, None) == spk.OK
