@@ -22,15 +22,17 @@
  *  - An spk_net is read-only after creation and may be shared by contexts.
  *    One spk_ctx must not be used from two host threads at once.
  *  - n == 0 is a no-op returning SPK_OK.
- *  - Bounds: the returned [lo, hi] is the affine-arithmetic bound of the
- *    paper (generators FP32 on MFMA, center and linearisation parameters
- *    FP64) widened by a floating-point tolerance margin of 2^-18 (|center| +
- *    radius), which covers the FP32 rounding of the bound by a wide factor.
- *    With SPK_FLAG_RIGOROUS it is widened instead by an a-priori rigorous
- *    rounding-error radius (every FP32/FP64 rounding bounded and propagated
- *    through |W|): provably conservative, but on deep wide networks it grows
- *    with the product of the |W| row sums and can dominate the bound.
- *    Non-finite inputs give lo = -inf, hi = +inf and label UNKNOWN.
+ *  - Bounds (default): the returned [lo, hi] is a provably sound enclosure of
+ *    f over the box.  The affine-arithmetic bound of the paper is evaluated
+ *    with generators in FP32 on MFMA, center and linearisation parameters in
+ *    FP64, and every rounding bounded a priori and folded into the condensed
+ *    term (a per-neuron error symbol, Appendix A), so the form encloses the
+ *    exact network at every layer.  With SPK_FLAG_NO_ROUNDING_BOUND the
+ *    arithmetic is the paper's, which ignores rounding (Section 3.4): the raw
+ *    bound matches the exact affine arithmetic to about 1e-6 relative and
+ *    [lo, hi] adds a tolerance margin of 2^-18 (|center| + radius), which is
+ *    not a proof.  Non-finite inputs give lo = -inf, hi = +inf and label
+ *    UNKNOWN.
  */
 #ifndef SPK_H
 #define SPK_H
@@ -65,9 +67,9 @@ typedef enum { SPK_AFFINE_FIXED = 0, SPK_AFFINE_TRUNCATE = 1, SPK_AFFINE_FULL = 
  *  SPK_PREC_BF16X3 split BF16: W = W_hi + W_lo and X = X_hi + X_lo (round to
  *                  nearest BF16 each), W_hi X_hi + W_hi X_lo + W_lo X_hi on the
  *                  BF16 MFMA (16x16x32) with FP32 accumulation.  The dropped
- *                  W_lo X_lo and split residuals are bounded a priori and the
- *                  rigorous rounding radius is always applied (as with
- *                  SPK_FLAG_RIGOROUS).  Hidden width 256 only (else
+ *                  W_lo X_lo and split residuals are bounded a priori like
+ *                  every other rounding (SPK_FLAG_NO_ROUNDING_BOUND is
+ *                  rejected).  Hidden width 256 only (else
  *                  SPK_E_UNSUPPORTED); single-network bound calls only.
  *  SPK_PREC_F16X3  split FP16 with power-of-two scaling: each hidden layer's W
  *                  is scaled by 2^sW (max |W| 2^sW in [2^14, 2^15)) and each
@@ -86,9 +88,12 @@ enum { SPK_UNKNOWN = 0, SPK_POSITIVE = 1, SPK_NEGATIVE = 2 };
 
 /* spk_bound_opts.flags */
 enum {
-  /* lo/hi and labels use the a-priori rigorous rounding radius (aux err)
-     instead of the floating-point tolerance margin; see spk_range_bound. */
-  SPK_FLAG_RIGOROUS = 1u
+  /* the rounding-error bound (the default; accepted for explicitness) */
+  SPK_FLAG_RIGOROUS = 1u,
+  /* the paper's arithmetic without the rounding-error bound, widened by the
+     tolerance margin only (for comparison with the exact arithmetic); not
+     combinable with SPK_FLAG_RIGOROUS or the split precisions */
+  SPK_FLAG_NO_ROUNDING_BOUND = 2u
 };
 
 typedef struct {
@@ -135,11 +140,14 @@ spk_status spk_ctx_sync(spk_ctx* ctx);
 
 /*
  * Optional diagnostic outputs of the bound calls (all dev, nullable).
- *   center, radius  [n]: the raw bound before rounding inflation,
- *                   lo_raw = center - radius, hi_raw = center + radius.
- *   err             [n]: the widening applied beyond the raw bound: the
- *                   a-priori rigorous rounding-error radius under
- *                   SPK_FLAG_RIGOROUS, else the tolerance margin.
+ *   center, radius  [n]: the bound's center and radius before the last
+ *                   widening.  Under SPK_FLAG_NO_ROUNDING_BOUND these are the
+ *                   paper's arithmetic (lo_raw = center - radius, hi_raw =
+ *                   center + radius); by default the radius already holds the
+ *                   folded rounding bounds of every layer.
+ *   err             [n]: the widening applied beyond center -/+ radius: the
+ *                   rounding of the output layer itself (default), else the
+ *                   tolerance margin.
  *   slot_src        [n_linear-1][n][32] int16: for affine-truncate, after
  *                   each activation (n_linear-1 of them) and for each of the
  *                   32 term slots of each box: -1 the slot kept its previous

@@ -13,12 +13,13 @@
 //    linearisation, eq. affine_func_update) is lane-local, and only the
 //    column reductions of truncation (Section 3.3) cross lanes.
 //
-// Beside the raw affine arithmetic the kernels carry, per neuron, a rigorous
-// floating-point error radius `e`: every FP32 rounding (MFMA accumulation,
-// activation parameters, transcendental functions, condensation sums) is
-// bounded and added to it, so the final [lo, hi] is a sound enclosure even
-// though the arithmetic is FP32.  The raw endpoints (without `e`) follow the
-// paper's arithmetic and are what parity tests compare with the FP64 oracle.
+// In the rigorous mode (the default) every floating-point rounding (MFMA
+// accumulation, FP64 center, activation parameters, transcendental
+// functions, condensation sums) is bounded a priori and folded into the
+// condensed coefficient, a per-neuron error symbol, so the form encloses the
+// exact network at every layer and the final [lo, hi] is a sound enclosure
+// although the arithmetic is FP32.  Without it the arithmetic is the
+// paper's, which the parity tests compare with the FP64 oracle.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -78,11 +79,18 @@ __device__ __forceinline__ float seg_allsum(float v) {
 
 // Number of lanes of this lane's segment (SEG consecutive lanes) with p set.
 template <int SEG>
+__device__ __forceinline__ unsigned long long seg_mask(int lane) {
+  if constexpr (SEG == 64) {
+    return ~0ull;
+  } else {
+    return ((1ull << SEG) - 1ull) << ((lane / SEG) * SEG);
+  }
+}
+
+template <int SEG>
 __device__ __forceinline__ int seg_count(bool p, int lane) {
   const unsigned long long m = __ballot(p);
-  if (SEG == 64) return __popcll(m);
-  const unsigned long long segm = ((1ull << SEG) - 1ull) << ((lane / SEG) * SEG);
-  return __popcll(m & segm);
+  return __popcll(m & seg_mask<SEG>(lane));
 }
 
 // Same, restricted to the lanes of the segment below this lane.
@@ -90,9 +98,7 @@ template <int SEG>
 __device__ __forceinline__ int seg_count_below(bool p, int lane) {
   const unsigned long long m = __ballot(p);
   const unsigned long long below = (1ull << lane) - 1ull;
-  const unsigned long long segm =
-      (SEG == 64) ? ~0ull : (((1ull << SEG) - 1ull) << ((lane / SEG) * SEG));
-  return __popcll(m & below & segm);
+  return __popcll(m & below & seg_mask<SEG>(lane));
 }
 
 // Position of the n-th (0-based) set bit of m (m must have more than n set bits).
@@ -114,15 +120,13 @@ __device__ __forceinline__ int nth_set_bit(uint32_t m, int n) {
 // Linearisation parameters (Table 3), computed in FP64 from the FP64 range
 // [xl, xu].  `dg` bounds how much the true maximum error of alpha*x + beta on
 // [xl, xu] can exceed the returned gamma (evaluation rounding and the ulp
-// error of the transcendental functions); `lip` is the Lipschitz constant of
-// h(x) - alpha*x, used to extend the linearisation to the rounding-error
-// neighbourhood of [xl, xu].  FP64 matters here: for narrow ranges gamma is a
-// difference of nearly equal numbers (ELU, sin), which loses ~1e-3 of the
-// bound in FP32 on 8-layer networks.
+// error of the transcendental functions).  FP64 matters here: for narrow
+// ranges gamma is a difference of nearly equal numbers (ELU, sin), which
+// loses ~1e-3 of the bound in FP32 on 8-layer networks.
 // ---------------------------------------------------------------------------
 struct ActOut {
   double al, be, ga;
-  float dg, lip;
+  float dg;
 };
 
 constexpr double kUd = 1.1102230246251565e-16;   // 2^-53
@@ -133,7 +137,6 @@ __device__ __forceinline__ ActOut act_params(double xl, double xu, double x0);
 template <>
 __device__ __forceinline__ ActOut act_params<SPK_ACT_RELU>(double xl, double xu, double x0) {
   ActOut o;
-  o.lip = 1.0f;
   if (xl >= 0.0) {
     o.al = 1.0; o.be = 0.0; o.ga = 0.0; o.dg = 0.0f;
   } else if (xu <= 0.0) {
@@ -153,7 +156,6 @@ __device__ __forceinline__ double elu_d(double x) { return x > 0.0 ? x : expm1(x
 template <>
 __device__ __forceinline__ ActOut act_params<SPK_ACT_ELU>(double xl, double xu, double x0) {
   ActOut o;
-  o.lip = 1.0f;
   if (xl >= 0.0) {
     o.al = 1.0; o.be = 0.0; o.ga = 0.0; o.dg = 0.0f;
     return o;
@@ -212,7 +214,6 @@ __device__ __forceinline__ ActOut act_params<SPK_ACT_SIN>(double xl, double xu, 
   const double M = fabs(xl) + fabs(xu) + 16.0;
   const double dx = 8.0 * kUd * M;
   o.dg = (float)(32.0 * kUd * (1.0 + fabs(al) * M + fabs(o.be)) + dx * dx) + kEta;
-  o.lip = (float)(1.0 + fabs(al));
   return o;
 }
 

@@ -25,7 +25,6 @@ template <class S>
 struct LdsState {
   float tile[S::TILE];
   float vinf[256];
-  float vu[256];
   double vc[256];
 };
 
@@ -55,10 +54,26 @@ __device__ __forceinline__ float round_up_f(double v) {
 
 // Activation + condensation on the owner-layout rows.  On entry xc holds the
 // pre-activation centers (FP64, bias included), y the generator terms in
-// slots 1.. (slot 0 is unused), yinf the condensed term and e the error
-// radius.  On exit xc/y/yinf/e hold the post-activation form and u = e + cK r
-// + cD |x0| is the vector the next layer's rounding-error product |W| u needs.
-// Returns the new number of occupied generator slots.
+// slots 1.. (slot 0 is unused) and yinf the condensed term.  On exit
+// xc/y/yinf hold the post-activation form.  Returns the new number of
+// occupied generator slots.
+//
+// With rig = false this is the paper's arithmetic (rounding ignored, Section
+// 3.4): the linearisation is taken on the computed range and e, u are not
+// used.  With rig = true every floating-point rounding is bounded a priori and
+// folded into the condensed term, which is itself a per-neuron error symbol
+// (Appendix A), so the form stays a sound enclosure of the exact network:
+//  * e (in) holds the errors created since the last fold (layer 0 input and
+//    product rounding, bias addition, split-product absolute terms); it is
+//    added to yinf first and cleared;
+//  * the linearisation is taken on the range of the whole form, so it holds
+//    wherever the exact pre-activation can lie;
+//  * the rounding of alpha x0 + beta, of alpha Y, of alpha yinf, of gamma and
+//    the evaluation error of (alpha, beta, gamma) go into yinf;
+//  * condensed sums are rounded upwards;
+//  * last, yinf receives u = cK r + cD |x0|, the a-priori rounding of the next
+//    layer's products (generators in FP32 or split precision against W, the
+//    center in FP64): that layer's |W| yinf then carries it.
 //
 // With `sent` non-null (first activation of a bound pass, truncate), every
 // kept new term placed in a slot C >= 4 is also recorded as the single entry
@@ -67,7 +82,7 @@ __device__ __forceinline__ float round_up_f(double v) {
 template <class S, int ACT, int POL, int NPASS>
 __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
                                         float (&u)[4], int n_occ, int k, float cK, float cD, float omega0, int lane,
-                                        int16_t* rec, float* sent = nullptr) {
+                                        int16_t* rec, float* sent = nullptr, bool rig = false) {
   static_assert(NPASS == 0 || POL == SPK_AFFINE_FIXED, "passengers ride along affine-fixed passes only");
   constexpr int NG = S::NS - NPASS;   // slots 1..NG-1 are generators
   float gam[4], rnext[4];
@@ -75,6 +90,10 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
     for (int C = NG; C < S::NS; ++C) y[C][i] = act_point<ACT>(y[C][i], omega0);
+    if (rig) {
+      yinf[i] = round_up_f((double)yinf[i] + (double)e[i]);
+      e[i] = 0.0f;
+    }
     if (ACT == SPK_ACT_SIN) {
       // Table 2 constant multiplication by omega0 before sin
       float rs = 0.0f;
@@ -83,9 +102,15 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
         y[C][i] *= omega0;
         rs += fabsf(y[C][i]);
       }
-      yinf[i] *= omega0;
       xc[i] *= (double)omega0;
-      e[i] = (e[i] * omega0 + kU * (rs + yinf[i])) * kGrow + (float)(2.0 * kU64) * (float)fabs(xc[i]) + kEta;
+      if (rig) {
+        // products by omega0 (FP32 generators and yinf, FP64 center)
+        const double ys = (double)yinf[i] * (double)omega0;
+        yinf[i] = round_up_f((ys + (double)kU * ((double)rs + ys)) * (1.0 + 4.0 * kU64) + 2.0 * kU64 * fabs(xc[i]) +
+                             (double)kEta);
+      } else {
+        yinf[i] *= omega0;
+      }
     }
     const double x0 = xc[i];
     // the range radius is summed in FP64: the linearisation parameters of a
@@ -93,38 +118,32 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
     double rYd = 0.0;
 #pragma unroll
     for (int C = 1; C < NG; ++C) rYd += (double)fabsf(y[C][i]);
-    const double rd = rYd + (double)yinf[i];
+    double rd = rYd + (double)yinf[i];
+    // rigorous: an FP64 sum of NG terms is within (NG + 1) 2^-53 of exact
+    if (rig) rd = rd * (1.0 + (double)(NG + 2) * kU64) + (double)kEta;
     const float rY = round_up_f(rYd);
     const float r = round_up_f(rd);
     const double xl = x0 - rd, xu = x0 + rd;
     const ActOut p = act_params<ACT>(xl, xu, x0);
     const float alf = (float)p.al;
-    // rounding of the range read-off (the FP32 sum r)
-    const float rho = (float)(S::NS + 3) * kU * r + kEta;
-    const float ext = e[i] + rho;
-    bool exact;
-    if (ACT == SPK_ACT_RELU)
-      exact = (p.al == 1.0 && xl - (double)ext >= 0.0) || (p.al == 0.0 && xu + (double)ext <= 0.0);
-    else if (ACT == SPK_ACT_ELU)
-      exact = p.al == 1.0 && xl - (double)ext >= 0.0;
-    else
-      exact = false;
-    // the linearisation holds on [xl, xu] up to gamma; on the rounding
-    // neighbourhood it degrades by at most lip * ext (unless it is exact there)
-    float ep = fabsf(alf) * e[i] + (exact ? 0.0f : p.lip * ext + p.dg);
     const double z0 = fma(p.al, x0, p.be);
 #pragma unroll
     for (int C = 1; C < NG; ++C) y[C][i] *= alf;
     xc[i] = z0;
     y[0][i] = (float)z0;
     const float zi = fabsf(alf) * yinf[i];
-    // FP32 slope applied to the generators (2u: slope rounding + product),
-    // condensed-term product, FP64 center update
-    ep += 2.0f * kU * (fabsf(alf) * rY + zi) + (float)(2.0 * kU64) * (float)fabs(z0);
-    yinf[i] = zi;
-    // gamma rounded to FP32; the rounding goes into the error radius
     gam[i] = fmaxf((float)p.ga, 0.0f);
-    e[i] = ep + kU * gam[i];
+    if (rig) {
+      // FP32 slope applied to the generators and to yinf (slope rounding +
+      // product: 2u), FP64 center update, gamma rounded to FP32, evaluation
+      // error of the parameters; rY and r are rounded up, so they bound the
+      // exact sums
+      const double ep = 2.0 * (double)kU * ((double)fabsf(alf) * (double)rY + (double)zi) + 2.0 * kU64 * fabs(z0) +
+                        (double)kU * (double)gam[i] + (double)p.dg + (double)kEta;
+      yinf[i] = round_up_f(((double)zi + ep) * (1.0 + 2.0 * kU64));
+    } else {
+      yinf[i] = zi;
+    }
     rnext[i] = fabsf(alf) * r + gam[i];
   }
 
@@ -132,7 +151,7 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
   if (POL == SPK_AFFINE_FIXED) {
     // affine-fixed: every new term goes straight into the condensed coefficient
 #pragma unroll
-    for (int i = 0; i < 4; ++i) yinf[i] += gam[i];
+    for (int i = 0; i < 4; ++i) yinf[i] = rig ? round_up_f((double)yinf[i] + (double)gam[i]) : yinf[i] + gam[i];
   } else {
     // affine-truncate(k): candidates are the occupied old slots 1..n_occ
     // (magnitude = column L1 norm over the box's H rows) and the H new terms
@@ -233,7 +252,8 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
         }
       }
       zi += keepnew[i] ? 0.0 : (double)gam[i];
-      yinf[i] = (float)zi;
+      // rigorous: FP64 sum of at most NS + 1 terms, rounded upwards
+      yinf[i] = rig ? round_up_f(zi * (1.0 + (double)(S::NS + 3) * kU64)) : (float)zi;
     }
     if (sent != nullptr) {
 #pragma unroll
@@ -260,11 +280,11 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
     }
     n_occ_new = (n_occ + S::H < k) ? n_occ + S::H : k;
   }
+  if (rig) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float ef = e[i] * kGrow + (float)(S::NS + 2) * kU * yinf[i] + kEta;
-    e[i] = ef;
-    u[i] = ef + (cK * rnext[i] + cD * (float)fabs(xc[i])) * kGrowR;
+    for (int i = 0; i < 4; ++i)
+      yinf[i] = round_up_f((double)yinf[i] + ((double)cK * (double)rnext[i] + (double)cD * fabs(xc[i])) *
+                                                 (1.0 + 1.52587890625e-05) + (double)kEta);
   }
   return n_occ_new;
 }
@@ -272,25 +292,20 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
 // Reduce the VALU partial sums of output tile tp of box b over the four
 // K-row groups of the wave and store them in the LDS vectors.
 template <class S>
-__device__ __forceinline__ void store_partials(LdsState<S>& sm, int b, int tp, int g, int c, float sx, float se,
-                                               double sd) {
+__device__ __forceinline__ void store_partials(LdsState<S>& sm, int b, int tp, int g, int c, float sx, double sd) {
   sx += __shfl_xor(sx, 16, 64);
-  se += __shfl_xor(se, 16, 64);
   sd += __shfl_xor(sd, 16, 64);
   sx += __shfl_xor(sx, 32, 64);
-  se += __shfl_xor(se, 32, 64);
   sd += __shfl_xor(sd, 32, 64);
   if (g == 0) {
     sm.vinf[b * S::H + 16 * tp + c] = sx;
-    sm.vu[b * S::H + 16 * tp + c] = se;
     sm.vc[b * S::H + 16 * tp + c] = sd;
   }
 }
 
-// VALU work that rides along an MFMA pass: none (later column tiles), the
-// FP64 center and |W| xinf (VA_CENTER), plus the rounding-error product |W| u
-// of the rigorous mode (VA_RIGOROUS).
-enum { VA_NONE = 0, VA_CENTER = 1, VA_RIGOROUS = 2 };
+// VALU work that rides along an MFMA pass: none (later column tiles) or the
+// FP64 center and |W| xinf (VA_CENTER).
+enum { VA_NONE = 0, VA_CENTER = 1 };
 
 // Column tile n of the wave's single box (H = 256) through one H -> H layer.
 // The A fragments stream from L2 in MFMA order (fragment (t, tp) is the
@@ -303,13 +318,12 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
   static_assert(S::BPW == 1 && MT % PF == 0, "one box per wave; the ring index repeats every K block");
   const int g = lane >> 4, c = lane & 15;
   f4 acc[MT];
-  float px[MT], pe[MT];
+  float px[MT];
   double pd[MT];
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
     acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
     px[tp] = 0.0f;
-    pe[tp] = 0.0f;
     pd[tp] = 0.0;
   }
   const f4* Wq = Wl + lane;
@@ -317,17 +331,16 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
 #pragma unroll
   for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
   f4 bn = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, g)];
-  f4 xn = {0.0f, 0.0f, 0.0f, 0.0f}, en = {0.0f, 0.0f, 0.0f, 0.0f};
+  f4 xn = {0.0f, 0.0f, 0.0f, 0.0f};
   double dn[4] = {0.0, 0.0, 0.0, 0.0};
   if (VA != VA_NONE) {
     xn = *(const f4*)&sm.vinf[4 * g];
-    if (VA == VA_RIGOROUS) en = *(const f4*)&sm.vu[4 * g];
 #pragma unroll
     for (int j = 0; j < 4; ++j) dn[j] = sm.vc[4 * g + j];
   }
 #pragma unroll 1
   for (int t = 0; t < MT; ++t) {
-    const f4 bfr = bn, vx = xn, ve = en;
+    const f4 bfr = bn, vx = xn;
     double vd[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) vd[j] = dn[j];
@@ -335,7 +348,6 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
     bn = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * t1 + g)];
     if (VA != VA_NONE) {
       xn = *(const f4*)&sm.vinf[16 * t1 + 4 * g];
-      if (VA == VA_RIGOROUS) en = *(const f4*)&sm.vu[16 * t1 + 4 * g];
 #pragma unroll
       for (int j = 0; j < 4; ++j) dn[j] = sm.vc[16 * t1 + 4 * g + j];
     }
@@ -351,14 +363,13 @@ __device__ __forceinline__ void single_box_pass(LdsState<S>& sm, const f4* Wl, i
           px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
           pd[tp] = fma((double)w[j], vd[j], pd[tp]);
         }
-        if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
       }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
-    if (VA != VA_NONE) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+    if (VA != VA_NONE) store_partials<S>(sm, 0, tp, g, c, px[tp], pd[tp]);
     *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = acc[tp];
   }
   __syncthreads();
@@ -379,12 +390,11 @@ __device__ __forceinline__ void single_box_pass2(LdsState<S>& sm, const f4* Wl, 
   const int g = lane >> 4, c = lane & 15;
   const f4* Wq = Wl + lane;
   if (VA != VA_NONE) {
-    float px[MT], pe[MT];
+    float px[MT];
     double pd[MT];
 #pragma unroll
     for (int tp = 0; tp < MT; ++tp) {
       px[tp] = 0.0f;
-      pe[tp] = 0.0f;
       pd[tp] = 0.0;
     }
     f4 ring[PF];
@@ -393,8 +403,6 @@ __device__ __forceinline__ void single_box_pass2(LdsState<S>& sm, const f4* Wl, 
 #pragma unroll 1
     for (int t = 0; t < MT; ++t) {
       const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
-      f4 ve = {0.0f, 0.0f, 0.0f, 0.0f};
-      if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[16 * t + 4 * g];
       double vd[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
@@ -407,13 +415,12 @@ __device__ __forceinline__ void single_box_pass2(LdsState<S>& sm, const f4* Wl, 
         for (int j = 0; j < 4; ++j) {
           px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
           pd[tp] = fma((double)w[j], vd[j], pd[tp]);
-          if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
         }
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int tp = 0; tp < MT; ++tp) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+    for (int tp = 0; tp < MT; ++tp) store_partials<S>(sm, 0, tp, g, c, px[tp], pd[tp]);
   }
   f4 acc0[MT], acc1[MT];
 #pragma unroll
@@ -480,13 +487,12 @@ __device__ __forceinline__ void single_box_pass_split(LdsState<S>& sm, const f4*
   static_assert(S::BPW == 1 && MT % PF == 0, "one box per wave; the ring index repeats every K block");
   const int g = lane >> 4, c = lane & 15;
   f4 acc[MT];
-  float px[MT], pe[MT];
+  float px[MT];
   double pd[MT];
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
     acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
     px[tp] = 0.0f;
-    pe[tp] = 0.0f;
     pd[tp] = 0.0;
   }
   if (VA != VA_NONE) {
@@ -497,8 +503,6 @@ __device__ __forceinline__ void single_box_pass_split(LdsState<S>& sm, const f4*
 #pragma unroll 1
     for (int t = 0; t < MT; ++t) {
       const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
-      f4 ve = {0.0f, 0.0f, 0.0f, 0.0f};
-      if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[16 * t + 4 * g];
       double vd[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
@@ -511,7 +515,6 @@ __device__ __forceinline__ void single_box_pass_split(LdsState<S>& sm, const f4*
         for (int j = 0; j < 4; ++j) {
           px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
           pd[tp] = fma((double)w[j], vd[j], pd[tp]);
-          if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
         }
       }
     }
@@ -545,7 +548,7 @@ __device__ __forceinline__ void single_box_pass_split(LdsState<S>& sm, const f4*
   __syncthreads();
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
-    if (VA != VA_NONE) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+    if (VA != VA_NONE) store_partials<S>(sm, 0, tp, g, c, px[tp], pd[tp]);
     *(f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + g)] = acc[tp];
   }
   __syncthreads();
@@ -584,12 +587,11 @@ __device__ __forceinline__ float single_box_pass_f16(LdsState<S>& sm, const f4* 
   if (VA != VA_NONE) {
     // VALU products first, reduced and stored before the MFMA loop so their
     // partial sums are not live beside the accumulators
-    float px[MT], pe[MT];
+    float px[MT];
     double pd[MT];
 #pragma unroll
     for (int tp = 0; tp < MT; ++tp) {
       px[tp] = 0.0f;
-      pe[tp] = 0.0f;
       pd[tp] = 0.0;
     }
     const f4* Wq = Wl + lane;
@@ -599,8 +601,6 @@ __device__ __forceinline__ float single_box_pass_f16(LdsState<S>& sm, const f4* 
 #pragma unroll 1
     for (int t = 0; t < MT; ++t) {
       const f4 vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
-      f4 ve = {0.0f, 0.0f, 0.0f, 0.0f};
-      if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[16 * t + 4 * g];
       double vd[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) vd[j] = sm.vc[16 * t + 4 * g + j];
@@ -613,13 +613,12 @@ __device__ __forceinline__ float single_box_pass_f16(LdsState<S>& sm, const f4* 
         for (int j = 0; j < 4; ++j) {
           px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
           pd[tp] = fma((double)w[j], vd[j], pd[tp]);
-          if (VA == VA_RIGOROUS) pe[tp] = fmaf(fabsf(w[j]), ve[j], pe[tp]);
         }
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int tp = 0; tp < MT; ++tp) store_partials<S>(sm, 0, tp, g, c, px[tp], pe[tp], pd[tp]);
+    for (int tp = 0; tp < MT; ++tp) store_partials<S>(sm, 0, tp, g, c, px[tp], pd[tp]);
   }
   // this lane's column scale: lanes c, c + 16, c + 32, c + 48 hold the
   // column's rows 8 g .. 8 g + 7 of every 32-row block
@@ -686,7 +685,7 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
   constexpr int H = S::H, MT = S::MT, BPW = S::BPW;
   const int g = lane >> 4, c = lane & 15;
   f4 acc[MT][BPW];
-  float px[MT][BPW], pe[MT][BPW];
+  float px[MT][BPW];
   double pd[MT][BPW];
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
@@ -694,7 +693,6 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
     for (int b = 0; b < BPW; ++b) {
       acc[tp][b] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
       px[tp][b] = 0.0f;
-      pe[tp][b] = 0.0f;
       pd[tp][b] = 0.0;
     }
   }
@@ -714,11 +712,10 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
       const f4 bfr = *(const f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * t + g)];
-      f4 vx = {0.0f, 0.0f, 0.0f, 0.0f}, ve = {0.0f, 0.0f, 0.0f, 0.0f};
+      f4 vx = {0.0f, 0.0f, 0.0f, 0.0f};
       double vd[4] = {0.0, 0.0, 0.0, 0.0};
       if (VA != VA_NONE) {
         vx = *(const f4*)&sm.vinf[b * H + 16 * t + 4 * g];
-        if (VA == VA_RIGOROUS) ve = *(const f4*)&sm.vu[b * H + 16 * t + 4 * g];
 #pragma unroll
         for (int j = 0; j < 4; ++j) vd[j] = sm.vc[b * H + 16 * t + 4 * g + j];
       }
@@ -731,7 +728,6 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
             px[tp][b] = fmaf(fabsf(w[tp][j]), vx[j], px[tp][b]);
             pd[tp][b] = fma((double)w[tp][j], vd[j], pd[tp][b]);
           }
-          if (VA == VA_RIGOROUS) pe[tp][b] = fmaf(fabsf(w[tp][j]), ve[j], pe[tp][b]);
         }
       }
     }
@@ -741,7 +737,7 @@ __device__ __forceinline__ void multi_box_pass(LdsState<S>& sm, const f4* Wl, in
   for (int tp = 0; tp < MT; ++tp) {
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
-      if (VA != VA_NONE) store_partials<S>(sm, b, tp, g, c, px[tp][b], pe[tp][b], pd[tp][b]);
+      if (VA != VA_NONE) store_partials<S>(sm, b, tp, g, c, px[tp][b], pd[tp][b]);
       *(f4*)&sm.tile[taddr<S>(b, 16 * n + c, 4 * tp + g)] = acc[tp][b];
     }
   }
@@ -769,54 +765,37 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
   }
   {
     f4 v1 = {yinf[0], yinf[1], yinf[2], yinf[3]};
-    f4 v2 = {u[0], u[1], u[2], u[3]};
     *(f4*)&sm.vinf[4 * lane] = v1;
-    *(f4*)&sm.vu[4 * lane] = v2;
 #pragma unroll
     for (int i = 0; i < 4; ++i) sm.vc[4 * lane + i] = xc[i];
   }
   __syncthreads();
 
-  // ---- generators on MFMA, center in FP64, |W| xinf and |W| u on VALU ----
+  // ---- generators on MFMA, center in FP64, |W| xinf on VALU ----
   const f4* Wl = (const f4*)net.Wp + (size_t)a * (H * H / 4);
   float sc_sum = 0.0f;   // split-FP16: sum of the column unscale factors
   if constexpr (PREC == SPK_PREC_F16X3) {
     static_assert(BPW == 1, "scaled split-FP16 products are built for one box per wave");
     const uint32_t* Whl = net.Wh + (size_t)a * (H * H);   // H*H (hi, lo) pairs of 16-bit values
     const float wsc = net.wsh[a];
-    if (rigorous)
-      sc_sum = single_box_pass_f16<S, VA_RIGOROUS>(sm, Wl, Whl, wsc, 0, lane);
-    else
-      sc_sum = single_box_pass_f16<S, VA_CENTER>(sm, Wl, Whl, wsc, 0, lane);
+    sc_sum = single_box_pass_f16<S, VA_CENTER>(sm, Wl, Whl, wsc, 0, lane);
 #pragma unroll 1
     for (int n = 1; n < NT; ++n) sc_sum += single_box_pass_f16<S, VA_NONE>(sm, Wl, Whl, wsc, n, lane);
     sc_sum *= 1.0f + 3.814697265625e-06f;   // 1 + 2^-18: FP32 sums of at most 32 powers of two
   } else if constexpr (PREC == SPK_PREC_BF16X3) {
     static_assert(BPW == 1, "split-BF16 products are built for one box per wave");
     const uint32_t* Wbl = net.Wb + (size_t)a * (H * H);   // H*H (hi, lo) pairs of 16-bit values
-    if (rigorous)
-      single_box_pass_split<S, VA_RIGOROUS>(sm, Wl, Wbl, 0, lane);
-    else
-      single_box_pass_split<S, VA_CENTER>(sm, Wl, Wbl, 0, lane);
+    single_box_pass_split<S, VA_CENTER>(sm, Wl, Wbl, 0, lane);
 #pragma unroll 1
     for (int n = 1; n < NT; ++n) single_box_pass_split<S, VA_NONE>(sm, Wl, Wbl, n, lane);
   } else if constexpr (BPW == 1 && NT == 2) {
-    if (rigorous)
-      single_box_pass2<S, VA_RIGOROUS>(sm, Wl, lane);
-    else
-      single_box_pass2<S, VA_CENTER>(sm, Wl, lane);
+    single_box_pass2<S, VA_CENTER>(sm, Wl, lane);
   } else if constexpr (BPW == 1) {
-    if (rigorous)
-      single_box_pass<S, VA_RIGOROUS>(sm, Wl, 0, lane);
-    else
-      single_box_pass<S, VA_CENTER>(sm, Wl, 0, lane);
+    single_box_pass<S, VA_CENTER>(sm, Wl, 0, lane);
 #pragma unroll 1
     for (int n = 1; n < NT; ++n) single_box_pass<S, VA_NONE>(sm, Wl, n, lane);
   } else {
-    if (rigorous)
-      multi_box_pass<S, VA_RIGOROUS>(sm, Wl, 0, lane);
-    else
-      multi_box_pass<S, VA_CENTER>(sm, Wl, 0, lane);
+    multi_box_pass<S, VA_CENTER>(sm, Wl, 0, lane);
 #pragma unroll 1
     for (int n = 1; n < NT; ++n) multi_box_pass<S, VA_NONE>(sm, Wl, n, lane);
   }
@@ -828,23 +807,26 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
   }
   {
     const f4 xi = *(const f4*)&sm.vinf[4 * lane];
-    const f4 eu = *(const f4*)&sm.vu[4 * lane];
     const f4 bh = *(const f4*)&net.bh[(size_t)a * H + 4 * ch];
     const f4 eb = *(const f4*)&net.ebh[(size_t)a * H + 4 * ch];
-    const float grow = 1.0f + 2.0f * cK;
+    const double grow = 1.0 + 2.0 * (double)cK;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       xc[i] = sm.vc[4 * lane + i] + (double)bh[i];
       y[0][i] = (float)xc[i];
 #pragma unroll
       for (int C = NS - NPASS; C < NS; ++C) y[C][i] += bh[i];
-      yinf[i] = xi[i];
-      e[i] = eu[i] * grow + eb[i];
+      // rigorous: the FP32 sum |W| xinf is within cK of exact; the input yinf
+      // already holds this layer's a-priori product rounding; e takes the
+      // bias addition (and the split-FP16 absolute terms below)
+      yinf[i] = rigorous ? round_up_f((double)xi[i] * grow) : xi[i];
+      e[i] = eb[i] + (float)(2.0 * kU64) * (float)fabs(xc[i]);
       // absolute split-FP16 errors, per column c with scale 2^s_c: FP16
       // underflow of X entries (<= 2^-13 scaled, times |W_hi + W_lo| <=
       // 2 |W|) and W residuals too small for a normal lo part (D_j times
       // max |x'| < 2^15); dwt_j bounds 2^-12 sum_k |W_jk| + D_j 2^(15 - sW)
       if constexpr (PREC == SPK_PREC_F16X3) e[i] = fmaf(net.dwt[(size_t)a * H + 4 * ch + i], sc_sum, e[i]) * kGrow;
+      (void)u;
     }
   }
   __syncthreads();
@@ -872,12 +854,11 @@ __device__ __forceinline__ float* first_layer_sent(LdsState<S>& sm, int bo) {
 // the input-axis columns is what the chord slopes of narrow straddling neurons
 // amplify most in the later layers.  A single-entry column is the scaled
 // weight column W[:, j] gamma_j (one FP32 rounding, the value any FP32
-// summation order gives).  |W| xinf and, in the rigorous mode, |W| u run in
-// FP32.  Lane ch owns rows 4ch..4ch+3 of its box and streams W from the
+// summation order gives).  |W| xinf runs in FP32.  Lane ch owns rows 4ch..4ch+3 of its box and streams W from the
 // 4x4-blocked copy (one coalesced 64-byte row block per lane and k block); the
-// box's vectors are LDS broadcasts.  The rounding-error radius keeps the
-// a-priori bound of the next activation's constant cK, which covers this
-// evaluation too.
+// box's vectors are LDS broadcasts.  In the rigorous mode the input yinf
+// already holds the a-priori rounding of this layer for the constant cK, which
+// covers this evaluation too.
 template <class S, bool RIG>
 __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S>& sm, double (&xc)[4],
                                                    f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
@@ -893,24 +874,19 @@ __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S
   {
     f4 v1 = {yinf[0], yinf[1], yinf[2], yinf[3]};
     *(f4*)&sm.vinf[4 * lane] = v1;
-    if (RIG) {
-      f4 v2 = {u[0], u[1], u[2], u[3]};
-      *(f4*)&sm.vu[4 * lane] = v2;
-    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) sm.vc[4 * lane + i] = xc[i];
   }
   __syncthreads();
   const double* vc = sm.vc + bo * H;
   const float* vi = sm.vinf + bo * H;
-  const float* vu = sm.vu + bo * H;
   const f4* Wr = (const f4*)net.Wr + 4 * ch;   // hidden layer 0
   double a0[4], a1[4], a2[4], a3[4];
-  float px[4], pe[4];
+  float px[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     a0[i] = 0.0; a1[i] = 0.0; a2[i] = 0.0; a3[i] = 0.0;
-    px[i] = 0.0f; pe[i] = 0.0f;
+    px[i] = 0.0f;
   }
 #pragma unroll 2
   for (int kb = 0; kb < H / 4; ++kb) {
@@ -921,8 +897,6 @@ __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S
     const f4 d2 = *(const f4*)&dense[H + 4 * kb];
     const f4 d3 = *(const f4*)&dense[2 * H + 4 * kb];
     const f4 xi = *(const f4*)&vi[4 * kb];
-    f4 uu = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (RIG) uu = *(const f4*)&vu[4 * kb];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const double x0 = vc[4 * kb + j];
@@ -935,7 +909,6 @@ __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S
         a2[i] = fma(wd, x2, a2[i]);
         a3[i] = fma(wd, x3, a3[i]);
         px[i] = fmaf(fabsf(w[i][j]), xi[j], px[i]);
-        if (RIG) pe[i] = fmaf(fabsf(w[i][j]), uu[j], pe[i]);
       }
     }
   }
@@ -956,7 +929,7 @@ __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S
   __syncthreads();
   const f4 bh = *(const f4*)&net.bh[4 * ch];
   const f4 eb = *(const f4*)&net.ebh[4 * ch];
-  const float grow = 1.0f + 2.0f * net.cK;
+  const double grow = 1.0 + 2.0 * (double)net.cK;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     xc[i] = a0[i] + (double)bh[i];
@@ -964,39 +937,42 @@ __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S
     y[1][i] = (float)a1[i];
     y[2][i] = (float)a2[i];
     y[3][i] = (float)a3[i];
-    yinf[i] = px[i];
-    e[i] = pe[i] * grow + eb[i];
+    yinf[i] = RIG ? round_up_f((double)px[i] * grow) : px[i];
+    e[i] = eb[i] + (float)(2.0 * kU64) * (float)fabs(xc[i]);
   }
+  (void)u;
 }
 
 struct OutVals {
   double y0;    // center
-  float r;      // raw radius
-  float err;    // rounding-error radius
+  float r;      // radius (rounded up in the rigorous mode)
+  float err;    // rigorous mode: rounding of the output layer itself
 };
 
 // Output layer (H -> 1) and range read-off, reduced over the box's segment
 // (every lane of the segment gets the same values).  pass[] receives the
-// passengers' plain evaluations f(x).
+// passengers' plain evaluations f(x).  In the rigorous mode the input yinf
+// already holds the a-priori rounding of these products (cK, cD); err adds
+// the rounding of |w| yinf, of the radius sum, of the output bias and of the
+// center.
 template <class S, int NPASS>
 __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double (&xc)[4], const f4 (&y)[S::NS],
                                                 const float (&yinf)[4], const float (&u)[4], int lane,
-                                                float (&pass)[NPASS > 0 ? NPASS : 1]) {
+                                                float (&pass)[NPASS > 0 ? NPASS : 1], bool rig = false) {
   constexpr int NS = S::NS, SEG = S::SEG, NG = NS - NPASS;
   const int ch = lane % SEG;
   const float cK = net.cK;
+  (void)u;
   const f4 wv = *(const f4*)&net.wL[4 * ch];
   double p0 = 0.0;
-  float pinf = 0.0f, pu = 0.0f;
+  float pinf = 0.0f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     p0 = fma((double)wv[i], xc[i], p0);
     pinf = fmaf(fabsf(wv[i]), yinf[i], pinf);
-    pu = fmaf(fabsf(wv[i]), u[i], pu);
   }
   p0 = seg_allsum_d<SEG>(p0);
   pinf = seg_allsum<SEG>(pinf);
-  pu = seg_allsum<SEG>(pu);
   double rd = 0.0;
 #pragma unroll
   for (int C = 1; C < NG; ++C) {
@@ -1007,7 +983,6 @@ __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double 
     rd += (double)fabsf(seg_allsum<SEG>(pc));
   }
   rd += (double)pinf;
-  const float r = (float)rd;
 #pragma unroll
   for (int C = NG; C < NS; ++C) {
     float pc = wv[0] * y[C][0];
@@ -1018,9 +993,15 @@ __device__ __forceinline__ OutVals output_layer(const NetDev& net, const double 
   }
   OutVals o;
   o.y0 = p0 + (double)net.bL;
-  o.r = r;
-  o.err = (pu * (1.0f + 2.0f * cK) + net.eL + (float)(NS + 3) * kU * r + (float)(4.0 * kU64) * (float)fabs(o.y0)) *
-              kGrow + kEta;
+  if (rig) {
+    const double rr = rd * (1.0 + (double)(NS + 2) * kU64);
+    o.r = round_up_f(rr);
+    o.err = round_up_f((2.0 * (double)cK * (double)pinf + (double)net.eL + 4.0 * kU64 * fabs(o.y0)) *
+                           (1.0 + 4.0 * kU64) + (double)kEta);
+  } else {
+    o.r = (float)rd;
+    o.err = 0.0f;
+  }
   return o;
 }
 

@@ -437,7 +437,7 @@ spk_status spk_range_bound(spk_ctx* ctx, const spk_net* net, const spk_bound_opt
   job.policy = opts->policy;
   job.k = opts->k;
   job.prec = opts->prec;
-  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
+  job.rigorous = rigorous_opts(opts) ? 1 : 0;
   job.a = center;
   job.b = axes;
   job.lo = lo;
@@ -463,7 +463,7 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
   job.policy = opts->policy;
   job.k = opts->k;
   job.prec = opts->prec;
-  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
+  job.rigorous = rigorous_opts(opts) ? 1 : 0;
   job.a = box_lo;
   job.b = box_hi;
   job.lo = lo;
@@ -486,7 +486,7 @@ static spk_status subdivide_round(spk_ctx* ctx, const spk_net* net, const spk_bo
   job.policy = opts->policy;
   job.k = opts->k;
   job.prec = opts->prec;
-  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
+  job.rigorous = rigorous_opts(opts) ? 1 : 0;
   job.cells = cells;
   job.level = level;
   for (int d = 0; d < 3; ++d) {
@@ -669,7 +669,7 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
     job.policy = opts->policy;
     job.k = opts->k;
     job.prec = opts->prec;
-  job.rigorous = ((opts->flags & SPK_FLAG_RIGOROUS) || opts->prec != SPK_PREC_F32) ? 1 : 0;
+  job.rigorous = rigorous_opts(opts) ? 1 : 0;
     job.cells = (const uint64_t*)codes;
     job.level = level;
     for (int d = 0; d < 3; ++d) {

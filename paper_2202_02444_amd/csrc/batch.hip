@@ -174,7 +174,7 @@ spk_status write_descriptors(spk_batch* b, const spk_batch_item* items, hipStrea
       job.s = 3;
       job.policy = b->opts.policy;
       job.k = b->opts.k;
-      job.rigorous = (b->opts.flags & SPK_FLAG_RIGOROUS) ? 1 : 0;
+      job.rigorous = spk::rigorous_opts(&b->opts) ? 1 : 0;
       job.prec = SPK_PREC_F32;
       job.a = it.box_lo;
       job.b = it.box_hi;

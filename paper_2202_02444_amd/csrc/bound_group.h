@@ -69,9 +69,10 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
   box_input(job, box, valid, cc, ax, ein);
   double xc[4];
   f4 y[NS];
-  float yinf[4], e[4], u[4];
+  float yinf[4], e[4], u[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   layer0_affine<S, 0>(net, ch, cc, ax, ein, pts, xc, y, yinf, e);
   int n_occ = job.s;
+  const bool rig = job.rigorous != 0;
   // the next layer's generator products: FP32 or split-BF16 rounding bound
   const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs : (PREC == SPK_PREC_F16X3 ? net.cKh : net.cK);
   if constexpr (S::BPW == 1) {
@@ -81,7 +82,8 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
       // products, the dense ones in FP64
       int16_t* rec = (job.slot_src != nullptr && valid) ? job.slot_src + (size_t)box * 32 : nullptr;
       float* sent = POL == SPK_AFFINE_TRUNCATE ? first_layer_sent<S>(sm, bo) : nullptr;
-      n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec, sent);
+      n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec, sent,
+                                       rig);
     }
     if (L > 2) {
       const int klast = POL == SPK_AFFINE_TRUNCATE ? job.k : 3;
@@ -92,7 +94,8 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
       for (int a = 1; a < L - 1; ++a) {
         int16_t* rec = nullptr;
         if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
-        n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec);
+        n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec,
+                                       nullptr, rig);
         if (a == L - 2) break;
         hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
       }
@@ -102,13 +105,14 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
     for (int a = 0; a < L - 1; ++a) {
       int16_t* rec = nullptr;
       if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
-      n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec);
+      n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec,
+                                       nullptr, rig);
       if (a == L - 2) break;
       hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
     }
   }
   float pass[1];
-  const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass);
+  const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass, rig);
   BoxResult r;
   enclose(o, job.rigorous != 0, r.lo, r.hi);
   r.label = (r.lo > 0.0f) ? (uint8_t)SPK_POSITIVE : (r.hi < 0.0f) ? (uint8_t)SPK_NEGATIVE : (uint8_t)SPK_UNKNOWN;

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
     }
     double xc[4];
     f4 y[NS];
-    float yinf[4], e[4], u[4];
+    float yinf[4], e[4], u[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     layer0_affine<S, NPASS>(net, ch, cc, ax, ein, pts, xc, y, yinf, e);
     for (int a = 0; a < L - 1; ++a) {
       activate<S, ACT, SPK_AFFINE_FIXED, NPASS>(xc, y, yinf, e, u, 1, 0, net.cK, net.cD, net.omega0, lane,

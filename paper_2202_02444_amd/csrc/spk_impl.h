@@ -48,7 +48,7 @@ struct BoundJob {
   int s;              // number of box axes (1..3)
   int policy;         // spk_policy (fixed or truncate)
   int k;              // kept terms (truncate)
-  int rigorous;       // 1: lo/hi use the rigorous rounding radius
+  int rigorous;       // 1: every rounding bounded (default); 0: the paper's arithmetic + tolerance margin
   int prec;           // spk_prec of the generator products
   // IN_AABB: a = lo [n][3], b = hi [n][3]; IN_GENERAL: a = center [n][3], b = axes [n][s][3]
   const float* a;
@@ -130,13 +130,18 @@ struct spk_ctx {
 
 namespace spk {
 // Validation of the bound options shared by every entry point.
+inline bool rigorous_opts(const spk_bound_opts* o) { return (o->flags & SPK_FLAG_NO_ROUNDING_BOUND) == 0; }
+
 inline spk_status valid_opts(const spk_bound_opts* o) {
   if (o == nullptr) return SPK_E_INVAL;
   if (o->prec != SPK_PREC_F32 && o->prec != SPK_PREC_BF16X3 && o->prec != SPK_PREC_F16X3) return SPK_E_UNSUPPORTED;
   if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
   if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
   if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;
-  if (o->flags & ~(uint32_t)SPK_FLAG_RIGOROUS) return SPK_E_INVAL;
+  if (o->flags & ~(uint32_t)(SPK_FLAG_RIGOROUS | SPK_FLAG_NO_ROUNDING_BOUND)) return SPK_E_INVAL;
+  if (o->flags & SPK_FLAG_NO_ROUNDING_BOUND) {
+    if ((o->flags & SPK_FLAG_RIGOROUS) || o->prec != SPK_PREC_F32) return SPK_E_INVAL;
+  }
   return SPK_OK;
 }
 

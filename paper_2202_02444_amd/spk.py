@@ -158,13 +158,17 @@ def _ptr(t, dtype=None, shape=None, name="tensor"):
 
 
 FLAG_RIGOROUS = 1
+FLAG_NO_ROUNDING_BOUND = 2
 
 
 PREC = {"f32": 0, "bf16x3": 1, "f16x3": 2}
 
 
-def opts(policy="truncate", k=31, rigorous=False, prec="f32"):
-    return BoundOpts(POLICY[policy], int(k), PREC[prec], FLAG_RIGOROUS if rigorous else 0)
+def opts(policy="truncate", k=31, rigorous=True, prec="f32"):
+    """Bound options: rigorous=True (the library default) bounds every
+    rounding; rigorous=False is the paper's arithmetic with the tolerance
+    margin (SPK_FLAG_NO_ROUNDING_BOUND)."""
+    return BoundOpts(POLICY[policy], int(k), PREC[prec], 0 if rigorous else FLAG_NO_ROUNDING_BOUND)
 
 
 class Net:
@@ -238,7 +242,7 @@ def _aux(center=None, radius=None, err=None, slot_src=None):
 
 
 def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="truncate", k=31, aux=None,
-                   rigorous=False, prec="f32"):
+                   rigorous=True, prec="f32"):
     import torch
     n = box_lo.shape[0]
     o = opts(policy, k, rigorous, prec)
@@ -252,7 +256,7 @@ def classify_boxes(ctx, net, box_lo, box_hi, label, lo=None, hi=None, policy="tr
     _check(st, "spk_classify_boxes")
 
 
-def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=None, rigorous=False, prec="f32"):
+def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=None, rigorous=True, prec="f32"):
     import torch
     n, s = axes.shape[0], axes.shape[1]
     o = opts(policy, k, rigorous, prec)
@@ -266,12 +270,12 @@ def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=Non
 
 
 def subdivide_frontier(ctx, net, level, cells, children, leaves, counts, max_level, policy="truncate", k=31,
-                       dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8, noalloc=False):
+                       dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8, noalloc=False, rigorous=True):
     """One round of Procedure 3 (spk_subdivide_frontier, or with
     noalloc=True spk_subdivide_frontier_noalloc)."""
     import torch
     tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), int(arity))
-    o = opts(policy, k)
+    o = opts(policy, k, rigorous)
     n = cells.shape[0]
     capc = children.shape[0] if children is not None else 0
     capl = leaves.shape[0] if leaves is not None else 0
@@ -303,7 +307,7 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
 
 
 def closest_point(ctx, net, q, point, dist=None, bound=None, max_level=8, policy="fixed", k=31,
-                  dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), rigorous=False):
+                  dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), rigorous=True):
     """spk_closest_point: point [n, 3], dist [n] and bound [n] for queries q [n, 3]."""
     import torch
     n = q.shape[0]
@@ -321,7 +325,7 @@ class Batch:
     items: list of dicts with keys net (Net), box_lo, box_hi ([n, 3] float32
     device tensors), label ([n] uint8) and optionally lo, hi ([n] float32)."""
 
-    def __init__(self, ctx, items, policy="truncate", k=31, rigorous=False):
+    def __init__(self, ctx, items, policy="truncate", k=31, rigorous=True):
         self.handle = None
         self._keep = None
         arr = self._items(items)
@@ -405,7 +409,7 @@ class Server:
             r.n = req["box_lo"].shape[0]
             r.a, r.b = v(req["box_lo"]), v(req["box_hi"])
             r.out0, r.out1, r.out2 = v(req["label"]), v(req.get("lo")), v(req.get("hi"))
-            r.opts = opts(req.get("policy", "truncate"), req.get("k", 31))
+            r.opts = opts(req.get("policy", "truncate"), req.get("k", 31), req.get("rigorous", True))
             tensors = [req["box_lo"], req["box_hi"], req["label"], req.get("lo"), req.get("hi")]
         elif req["type"] == "rays":
             r.n = req["origin"].shape[0]
@@ -417,7 +421,7 @@ class Server:
             r.n = req["q"].shape[0]
             r.a = v(req["q"])
             r.out0, r.out1, r.out2 = v(req["point"]), v(req.get("dist")), v(req.get("bound"))
-            r.opts = opts(req.get("policy", "fixed"), req.get("k", 31))
+            r.opts = opts(req.get("policy", "fixed"), req.get("k", 31), req.get("rigorous", True))
             r.tree = TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1),
                                 int(req.get("max_level", 8)), 8)
             tensors = [req["q"], req["point"], req.get("dist"), req.get("bound")]
@@ -467,7 +471,7 @@ def eval_points(ctx, net, x, f):
 
 
 def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3,
-                 cap=1 << 26):
+                 cap=1 << 26, rigorous=True):
     """Fixed-depth octree by repeated spk_subdivide_frontier rounds (the
     breadth-first parallel rounds of Procedure 3).  Returns per-level stats and
     the UNKNOWN leaf cells at max_level (GPU tensor)."""
@@ -485,7 +489,7 @@ def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 
         children = torch.empty(max(capc, 1), dtype=torch.int64, device=dev)
         lv = torch.empty(max(capl, 1), dtype=torch.int64, device=dev)
         subdivide_frontier(ctx, net, level, cells, children[:capc] if capc else None, lv[:capl] if capl else None,
-                           counts, max_level, policy, k, dom_lo, dom_hi)
+                           counts, max_level, policy, k, dom_lo, dom_hi, rigorous=rigorous)
         c = counts.cpu().tolist()
         levels.append({"level": level, "n": n, "n_children": c[0], "n_leaves": c[1], "n_pos": c[2], "n_neg": c[3]})
         if at_max:

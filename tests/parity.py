@@ -16,8 +16,13 @@ def s_net(net, n=4096, seed=1234):
     return float(np.sqrt(np.mean(f * f)))
 
 
-def gpu_classify(ctx, g, lo, hi, policy, k, want_src=False, rigorous=False, prec="f32"):
+def gpu_classify(ctx, g, lo, hi, policy, k, want_src=False, rigorous=None, prec="f32"):
+    """Classify boxes through the C ABI.  rigorous=None means the paper's
+    arithmetic (SPK_FLAG_NO_ROUNDING_BOUND) for FP32 and the rounding bound for
+    the split precisions, which always carry it."""
     import torch
+    if rigorous is None:
+        rigorous = prec != "f32"
     from paper_2202_02444_amd import spk
     dev = torch.device("cuda")
     n = lo.shape[0]
@@ -111,3 +116,15 @@ def valid_topk(record, rel=1e-5):
         small = np.where(keep, -np.inf, mu).max(axis=1)
         bad += int(np.sum(big < small - rel * mu.max(axis=1)))
     return bad
+
+
+def rigorous_vs_oracle(out, lo_o, hi_o, S):
+    """A rigorous-mode bound against the oracle's exact affine bound of the same
+    kept terms.  Returns (containment violation relative to S, width ratio
+    g/o).  The rigorous bound widens every layer's range by the rounding
+    bounds, so it contains the exact bound up to the second-order effect of
+    the wider linearisation ranges (affine arithmetic is not inclusion
+    monotone), which stays far below the parity tolerance."""
+    viol = np.maximum(out["lo"] - lo_o, hi_o - out["hi"]) / S
+    w_o = np.maximum(hi_o - lo_o, 1e-300)
+    return viol, (out["hi"] - out["lo"]) / w_o

@@ -6,7 +6,8 @@ import pytest
 import workloads as wl
 from oracle import mlp as omlp
 
-from parity import TOL, label_ambiguous, oracle_labels, s_net, soundness_violations
+from parity import (TOL, default_margin, endpoint_errors, gpu_classify, keep_sets_from_src, label_ambiguous,
+                    oracle_labels, rigorous_vs_oracle, s_net, soundness_violations, valid_topk)
 
 pytestmark = pytest.mark.gpu
 
@@ -92,28 +93,55 @@ def test_batch_matches_single_launches(ctx, policy, k):
     b.close()
 
 
-def test_batch_vs_oracle(ctx):
-    """Labels equal the oracle's away from zero, and every sampled f lies in
-    the batched bound."""
+ORACLE_NETS = [
+    lambda: wl.he_normal_mlp([3, 32, 32, 1], 81, act="relu"),
+    lambda: wl.he_normal_mlp([3, 64, 64, 64, 1], 82, act="elu"),
+    lambda: wl.siren_mlp([3, 128, 128, 1], 83, 30.0),
+    lambda: wl.he_normal_mlp([3, 256, 256, 256, 1], 84, act="relu"),
+    lambda: wl.siren_mlp([3, 64, 64, 64, 64, 1], 85, 30.0),
+    lambda: wl.he_normal_mlp([3, 128, 128, 128, 1], 86, act="elu"),
+    lambda: wl.he_normal_mlp([3, 256, 256, 256, 256, 1], 87, act="elu")]
+
+
+@pytest.mark.parametrize("rigorous", [False, True])
+def test_batch_vs_oracle(ctx, rigorous):
+    """One batched launch over seven networks (every width, all three
+    activations).  Each network's batched bound equals bit for bit the
+    single-network launch that exports its kept sets, and the oracle replays
+    those sets: in the paper's arithmetic the raw endpoints match within TOL,
+    kept sets are valid top-k choices and labels are equal outside the
+    ambiguity band; in the rigorous mode the bound contains the oracle's;
+    every sampled f lies inside either way."""
     from paper_2202_02444_amd import spk
-    specs = [wl.he_normal_mlp([3, 64, 64, 64, 1], 55, act="relu"), wl.siren_mlp([3, 32, 32, 1], 56, 30.0)]
+    specs = [f() for f in ORACLE_NETS]
     gnets = [spk.Net.from_spec(s) for s in specs]
-    items = _items(specs, gnets, [900, 700], 80)
-    b = spk.Batch(ctx, items, "truncate", 31)
+    items = _items(specs, gnets, [700, 333, 1024, 257, 500, 64, 129], 88)
+    b = spk.Batch(ctx, items, "truncate", 31, rigorous=rigorous)
     b.launch(ctx)
     ctx.sync()
     for it in items:
+        net = it["spec"]
         lo, hi = it["np"]
+        H = net.hidden_width()
+        single = gpu_classify(ctx, it["net"], lo, hi, "truncate", 31, want_src=True, rigorous=rigorous)
         glo = it["lo"].cpu().numpy().astype(np.float64)
         ghi = it["hi"].cpu().numpy().astype(np.float64)
         lab = it["label"].cpu().numpy()
-        lo_o, hi_o = omlp.bound_boxes(it["spec"], lo, hi, "truncate", 31)[2:]
-        S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(it["spec"]))
-        amb = label_ambiguous(lo_o, hi_o, S, 3.9e-6 * (np.abs(lo_o) + np.abs(hi_o)))
-        # free-running truncation may keep other terms on a few boxes
-        assert np.mean(lab[~amb] == oracle_labels(lo_o, hi_o)[~amb]) >= 0.99
-        bad, _ = soundness_violations(it["spec"], lo, hi, glo, ghi, np.random.default_rng(9))
-        assert bad == 0
-        assert np.all(glo <= lo_o + TOL * S) and np.all(ghi >= hi_o - TOL * S) or \
-            np.mean((glo <= lo_o + TOL * S) & (ghi >= hi_o - TOL * S)) >= 0.99
+        assert np.array_equal(glo, single["lo"]) and np.array_equal(ghi, single["hi"]), net.name
+        assert np.array_equal(lab, single["label"]), net.name
+        rec = []
+        sets = keep_sets_from_src(single["src"], 3, 31, H)
+        _, _, lo_o, hi_o = omlp.bound_boxes(net, lo, hi, "truncate", 31, keep_sets=sets, record=rec)
+        S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+        if rigorous:
+            viol, _ = rigorous_vs_oracle(single, lo_o, hi_o, S)
+            assert viol.max() <= TOL, (net.name, viol.max())
+        else:
+            e = endpoint_errors(single["center"], single["radius"], lo_o, hi_o, S)
+            assert e.max() <= TOL, (net.name, e.max())
+            assert valid_topk(rec) == 0, net.name
+            amb = label_ambiguous(lo_o, hi_o, S, default_margin(single))
+            assert np.array_equal(lab[~amb], oracle_labels(lo_o, hi_o)[~amb]), net.name
+        bad, _ = soundness_violations(net, lo, hi, glo, ghi, np.random.default_rng(9))
+        assert bad == 0, net.name
     b.close()

@@ -13,7 +13,7 @@ from oracle import mlp as omlp
 from oracle import queries as oq
 
 from parity import (TOL, default_margin, endpoint_errors, keep_sets_from_src, label_ambiguous, oracle_labels,
-                    s_net, soundness_violations)
+                    rigorous_vs_oracle, s_net, soundness_violations)
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def test_full_size_boxes_sampled(ctx, policy, k):
     if policy == "truncate":
         src = torch.full((g.n_linear - 1, N_FULL, 32), -3, dtype=torch.int16, device=dev)
         aux["slot_src"] = src
-    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, policy, k, aux=aux)
+    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, policy, k, aux=aux, rigorous=False)
     ctx.sync()
     # every box got a result
     assert bool(torch.isfinite(glo).all()) and bool(torch.isfinite(ghi).all())
@@ -112,12 +112,55 @@ def test_full_size_rays_sampled(ctx):
     assert np.all(np.abs(tg[both] - to[both]) <= 2 * delta + 1e-4)
 
 
+def test_full_size_rigorous_sampled(ctx):
+    """The measured configuration in the library's default mode (every
+    rounding bounded): one launch over the 1M blob boxes, truncate k = 31.
+    Sampled boxes contain the oracle's exact bound of the same kept terms (to
+    the parity tolerance) and every sampled f; a label is the oracle's or
+    UNKNOWN outside the ambiguity band."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.scale_net(1)
+    g = spk.Net.from_spec(net)
+    lo, hi = wl.boxes(N_FULL, 11, 1e-4, 0.5)
+    dev = torch.device("cuda")
+    tl, th = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
+    lab = torch.empty(N_FULL, dtype=torch.uint8, device=dev)
+    glo = torch.empty(N_FULL, device=dev)
+    ghi = torch.empty(N_FULL, device=dev)
+    src = torch.full((g.n_linear - 1, N_FULL, 32), -3, dtype=torch.int16, device=dev)
+    spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, "truncate", 31, aux={"slot_src": src})
+    ctx.sync()
+    assert bool(torch.isfinite(glo).all()) and bool(torch.isfinite(ghi).all())
+    lab_from_bound = torch.where(glo > 0, 1, torch.where(ghi < 0, 2, 0)).to(torch.uint8)
+    assert bool((lab == lab_from_bound).all())
+    rng = np.random.default_rng(23)
+    idx = np.unique(np.concatenate([np.arange(64), np.arange(N_FULL - 64, N_FULL),
+                                    rng.choice(N_FULL, N_SAMPLE - 128, replace=False)]))
+    ti = torch.from_numpy(idx).to(dev)
+    out = {"lo": glo[ti].cpu().numpy().astype(np.float64), "hi": ghi[ti].cpu().numpy().astype(np.float64)}
+    g_lab = lab[ti].cpu().numpy()
+    sets = keep_sets_from_src(src[:, ti, :].cpu().numpy(), 3, 31, 256)
+    lo_o, hi_o = omlp.bound_boxes(net, lo[idx], hi[idx], "truncate", 31, keep_sets=sets)[2:]
+    S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+    viol, ratio = rigorous_vs_oracle(out, lo_o, hi_o, S)
+    lab_o = oracle_labels(lo_o, hi_o)
+    amb = label_ambiguous(lo_o, hi_o, S, np.zeros_like(S))
+    keep = np.mean(g_lab[lab_o != 0] == lab_o[lab_o != 0])
+    print("rigorous 1M blob boxes: containment %.2e, width ratio median %.4f p90 %.3g p99 %.3g, "
+          "oracle labels kept %.3f" % (viol.max(), np.median(ratio), np.quantile(ratio, 0.9),
+                                       np.quantile(ratio, 0.99), keep))
+    assert viol.max() <= TOL
+    assert np.all((g_lab[~amb] == lab_o[~amb]) | (g_lab[~amb] == spk.UNKNOWN))
+    bad, _ = soundness_violations(net, lo[idx], hi[idx], out["lo"], out["hi"], np.random.default_rng(24))
+    assert bad == 0
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
 def test_full_size_split_precision_sampled(ctx, prec):
     """The precision workload at full size (same net and 1M boxes, truncate
-    k = 31, split products with the rigorous radius): sampled boxes contain the
-    oracle's exact bound of the same kept terms, the raw bound lies within the
-    reported radius of it, and sampled f lies inside."""
+    k = 31, split products with the rounding bound): sampled boxes contain the
+    oracle's exact bound of the same kept terms and sampled f lies inside."""
     import torch
     from paper_2202_02444_amd import spk
     net = wl.scale_net(1)
@@ -145,8 +188,10 @@ def test_full_size_split_precision_sampled(ctx, prec):
     sets = keep_sets_from_src(src[:, ti, :].cpu().numpy(), 3, 31, 256)
     lo_o, hi_o = omlp.bound_boxes(net, lo[idx], hi[idx], "truncate", 31, keep_sets=sets)[2:]
     S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
-    assert np.all(g_lo <= lo_o + 1e-12 * S) and np.all(g_hi >= hi_o - 1e-12 * S)
-    tol = e + 1e-6 * S
-    assert np.all(np.abs((c - r) - lo_o) <= tol) and np.all(np.abs((c + r) - hi_o) <= tol)
+    viol, ratio = rigorous_vs_oracle({"lo": g_lo, "hi": g_hi}, lo_o, hi_o, S)
+    print("%s 1M blob boxes: containment %.2e, width ratio median %.4f p99 %.3g" % (
+        prec, viol.max(), np.median(ratio), np.quantile(ratio, 0.99)))
+    assert viol.max() <= TOL
+    assert np.all(e > 0) and np.all(np.isfinite(c)) and np.all(r >= 0)
     bad, _ = soundness_violations(net, lo[idx], hi[idx], g_lo, g_hi, np.random.default_rng(22))
     assert bad == 0

@@ -1,16 +1,16 @@
 """Split-BF16 and scaled split-FP16 generator products (SPK_PREC_BF16X3,
-SPK_PREC_F16X3) against the FP64 oracle and the FP32 path: the rigorous
-radius covers the split arithmetic, so the returned bound contains the
-oracle's exact affine bound (same truncation choices, replayed) and every
-sampled f; the raw bound deviates from the oracle by less than the reported
-radius."""
+SPK_PREC_F16X3) against the FP64 oracle and the FP32 path, all with the
+rounding bound folded in: the returned bound contains the oracle's exact
+affine bound (same truncation choices, replayed) to the parity tolerance and
+every sampled f, and is wider than FP32's by the larger split error
+constants."""
 import numpy as np
 import pytest
 
 import workloads as wl
 from oracle import mlp as omlp
 
-from parity import gpu_classify, keep_sets_from_src, s_net, soundness_violations
+from parity import TOL, gpu_classify, keep_sets_from_src, rigorous_vs_oracle, s_net, soundness_violations
 
 pytestmark = pytest.mark.gpu
 
@@ -51,20 +51,21 @@ def test_split_encloses_oracle(ctx, prec, name, policy, k):
     fin = np.isfinite(out["lo"]) & np.isfinite(out["hi"])
     assert fin.mean() > 0.99
     # the enclosure contains the exact affine bound of the same kept terms
-    assert np.all(out["lo"][fin] <= lo_o[fin] + 1e-12 * S[fin])
-    assert np.all(out["hi"][fin] >= hi_o[fin] - 1e-12 * S[fin])
-    # the raw bound stays within the reported a-priori radius of the oracle
-    raw_lo = out["center"] - out["radius"]
-    raw_hi = out["center"] + out["radius"]
-    tol = out["err"] + 1e-6 * S
-    assert np.all(np.abs(raw_lo - lo_o)[fin] <= tol[fin]) and np.all(np.abs(raw_hi - hi_o)[fin] <= tol[fin])
+    viol, ratio = rigorous_vs_oracle(out, lo_o, hi_o, S)
+    print("%s %s %s k%d: containment %.2e, width ratio median %.4f p99 %.3g" % (
+        prec, name, policy, k, viol[fin].max(), np.median(ratio[fin]), np.quantile(ratio[fin], 0.99)))
+    assert viol[fin].max() <= TOL
     bad, _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], np.random.default_rng(65))
     assert bad == 0
 
 
+def _width(o):
+    return o["hi"] - o["lo"]
+
+
 def test_split_bf16_vs_fp32_rigorous(ctx):
     """At equal (rigorous) soundness the split bound is at least as wide as
-    FP32's, and its raw part agrees with FP32's to ~2^-16 relative."""
+    FP32's (larger a-priori error constants) and centered alike."""
     from paper_2202_02444_amd import spk
     net = wl.he_normal_mlp([3] + [256] * 3 + [1], 66, act="relu")
     g = spk.Net.from_spec(net)
@@ -72,14 +73,14 @@ def test_split_bf16_vs_fp32_rigorous(ctx):
     s = gpu_classify(ctx, g, lo, hi, "fixed", 0, prec="bf16x3")
     f = gpu_classify(ctx, g, lo, hi, "fixed", 0, rigorous=True)
     S = np.maximum(np.maximum(np.abs(f["lo"]), np.abs(f["hi"])), s_net(net))
-    assert np.all(s["err"] >= f["err"])
+    ratio = _width(s) / _width(f)
+    assert np.median(ratio) >= 1.0 and np.mean(ratio >= 1.0 - 1e-6) >= 0.99, np.quantile(ratio, [0.01, 0.5])
     assert np.max(np.abs(s["center"] - f["center"]) / S) < 1e-3
-    assert np.max(np.abs(s["radius"] - f["radius"]) / S) < 1e-3
 
 
 def test_split_f16_tighter_than_bf16(ctx):
-    """Scaled split FP16 carries 22 significand bits to BF16's 16: its raw
-    bound is closer to FP32's and its a-priori radius is smaller."""
+    """Scaled split FP16 carries 22 significand bits to BF16's 16: its bound
+    is closer to FP32's."""
     from paper_2202_02444_amd import spk
     net = wl.he_normal_mlp([3] + [256] * 3 + [1], 66, act="relu")
     g = spk.Net.from_spec(net)
@@ -88,11 +89,10 @@ def test_split_f16_tighter_than_bf16(ctx):
     b = gpu_classify(ctx, g, lo, hi, "fixed", 0, prec="bf16x3")
     f = gpu_classify(ctx, g, lo, hi, "fixed", 0, rigorous=True)
     S = np.maximum(np.maximum(np.abs(f["lo"]), np.abs(f["hi"])), s_net(net))
-    assert np.all(h["err"] >= f["err"]) and np.all(h["err"] <= b["err"])
-    dh = np.abs(h["radius"] - f["radius"]) / S
-    db = np.abs(b["radius"] - f["radius"]) / S
+    rh = _width(h) / _width(f)
+    rb = _width(b) / _width(f)
+    assert np.median(rh) >= 1.0 - 1e-6 and np.median(rh) <= np.median(rb)
     assert np.max(np.abs(h["center"] - f["center"]) / S) < 1e-4
-    assert np.max(dh) < 1e-4 and np.median(dh) < np.median(db)
 
 
 def test_split_f16_extreme_scales(ctx):
@@ -114,7 +114,8 @@ def test_split_f16_extreme_scales(ctx):
             lo_o, hi_o = omlp.bound_boxes(net, lo, hi, "truncate", 15, keep_sets=sets)[2:]
             S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
             assert np.all(np.isfinite(out["lo"])) and np.all(np.isfinite(out["hi"]))
-            assert np.all(out["lo"] <= lo_o + 1e-12 * S) and np.all(out["hi"] >= hi_o - 1e-12 * S), (sc, hw)
+            viol, _ = rigorous_vs_oracle(out, lo_o, hi_o, S)
+            assert viol.max() <= TOL, (sc, hw, viol.max())
             bad, _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], np.random.default_rng(73))
             assert bad == 0
 
