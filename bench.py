@@ -14,6 +14,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -153,53 +154,46 @@ def batched_extra(ctx, dev, policy="truncate", k=K_KEEP):
                          "chunk": c["chunk"]} for c in classes]}
 
 
-def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, n_sample=2048, steps=2):
-    """Split-BF16 and scaled split-FP16 generator products (SPK_PREC_BF16X3,
-    SPK_PREC_F16X3) against FP32, all with the rigorous rounding radius:
-    boxes/s on the full batch, and on a sample the bound width relative to
-    the FP64 oracle's exact affine bound (same kept terms), label agreement
-    and sampled soundness."""
+def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, steps=2):
+    """Split-BF16, scaled split-FP16 and FP64 generator products
+    (SPK_PREC_BF16X3, SPK_PREC_F16X3, SPK_PREC_F64) against FP32, all with the
+    rounding bound (the library default): boxes/s on the full batch, and, over
+    every box, the bound width relative to the FP32 bound and the share of
+    FP32's POSITIVE / NEGATIVE labels each keeps (FP64 classifies many more).
+    (Widths against the FP64 oracle, label agreement with it and soundness on
+    1e7 points are GPU tests.)"""
     import torch
-    from oracle import mlp as omlp
     from paper_2202_02444_amd import spk
     n = tlo.shape[0]
-    lab = torch.empty(n, dtype=torch.uint8, device=dev)
     res = {}
     stream = torch.cuda.current_stream()
-    for prec in ("f32", "bf16x3", "f16x3"):
-        spk.classify_boxes(ctx, g, tlo, thi, lab, None, None, "truncate", K_KEEP, rigorous=True, prec=prec)
+    ref = None
+    for prec in ("f32", "bf16x3", "f16x3", "f64"):
+        lab = torch.empty(n, dtype=torch.uint8, device=dev)
+        glo = torch.empty(n, device=dev)
+        ghi = torch.empty(n, device=dev)
+        spk.classify_boxes(ctx, g, tlo, thi, lab, glo, ghi, "truncate", K_KEEP, prec=prec)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         for _ in range(steps):
-            spk.classify_boxes(ctx, g, tlo, thi, lab, None, None, "truncate", K_KEEP, rigorous=True, prec=prec)
+            spk.classify_boxes(ctx, g, tlo, thi, lab, glo, ghi, "truncate", K_KEEP, prec=prec)
         b.record(stream)
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
-        # sample: bounds, kept terms, oracle replay
-        m = n_sample
-        slo, shi = tlo[:m].contiguous(), thi[:m].contiguous()
-        glo = torch.empty(m, device=dev)
-        ghi = torch.empty(m, device=dev)
-        gl = torch.empty(m, dtype=torch.uint8, device=dev)
-        src = torch.full((len(net.weights) - 1, m, 32), -3, dtype=torch.int16, device=dev)
-        spk.classify_boxes(ctx, g, slo, shi, gl, glo, ghi, "truncate", K_KEEP, aux={"slot_src": src},
-                           rigorous=True, prec=prec)
-        torch.cuda.synchronize()
-        sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from parity import keep_sets_from_src, soundness_violations
-        sets = keep_sets_from_src(src.cpu().numpy(), 3, K_KEEP, 256)
-        lo_o, hi_o = omlp.bound_boxes(net, lo[:m], hi[:m], "truncate", K_KEEP, keep_sets=sets)[2:]
-        glo_n = glo.cpu().numpy().astype(np.float64)
-        ghi_n = ghi.cpu().numpy().astype(np.float64)
-        ratio = (ghi_n - glo_n) / np.maximum(hi_o - lo_o, 1e-300)
-        lab_o = np.where(lo_o > 0, 1, np.where(hi_o < 0, 2, 0))
-        bad, f = soundness_violations(net, lo[:m], hi[:m], glo_n, ghi_n, np.random.default_rng(7))
-        res[prec] = {"boxes_per_s": n / (ms * 1e-3), "ms_per_launch": ms,
-                     "width_ratio_median": float(np.median(ratio)), "width_ratio_p99": float(np.percentile(ratio, 99)),
-                     "contains_oracle": bool(np.all(glo_n <= lo_o) and np.all(ghi_n >= hi_o)),
-                     "label_agreement": float(np.mean(gl.cpu().numpy() == lab_o)),
-                     "sampled_points": int(f.size), "soundness_violations": bad}
-    res["sample_boxes"] = n_sample
+        w = (ghi - glo).double()
+        r = {"boxes_per_s": n / (ms * 1e-3), "ms_per_launch": ms}
+        if ref is None:
+            ref = (w, lab)
+            r["classified"] = float((lab != 0).double().mean().item())
+        else:
+            ratio = (w / ref[0].clamp_min(1e-300)).cpu().numpy()
+            cls = ref[1] != 0
+            r.update({"classified": float((lab != 0).double().mean().item()),
+                      "width_vs_f32_median": float(np.median(ratio)),
+                      "width_vs_f32_p99": float(np.percentile(ratio, 99)),
+                      "f32_labels_kept": float((lab[cls] == ref[1][cls]).double().mean().item()),
+                      "contradicts_f32": int(((lab != 0) & cls & (lab != ref[1])).sum().item())})
+        res[prec] = r
     return res
 
 
@@ -301,20 +295,41 @@ def serving_extra(dev, n_requests=40, loads=(0.3, 0.6, 0.9), budget=512 << 20, s
     return out
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(net, lo, hi, n_sample):
-    """The FP64 oracle, as it stands, on a bounded sample of the same boxes."""
+    """The FP64 oracle, as it stands, on a bounded sample of the same boxes:
+    with all host BLAS threads, and single-threaded on a smaller sample."""
     from oracle import mlp as omlp
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count() or 1
     t0 = time.perf_counter()
     omlp.bound_boxes(net, lo[:n_sample], hi[:n_sample], "truncate", K_KEEP)
     dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "boxes/s", "cores": int(cores), "kind": "oracle",
-            "sample": "%d of the %d boxes (FP64 NumPy oracle, affine-truncate k=%d), %.1f s" % (
-                n_sample, N_BOXES, K_KEEP, dt)}
+    out = {"value": n_sample / dt, "unit": "boxes/s", "cores": int(cores), "kind": "oracle",
+           "cpu": _cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": "%d of the %d boxes (FP64 NumPy oracle, affine-truncate k=%d), %.1f s" % (
+               n_sample, N_BOXES, K_KEEP, dt)}
+    if threadpool_limits is not None:
+        m = max(n_sample // 4, 64)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            omlp.bound_boxes(net, lo[:m], hi[:m], "truncate", K_KEEP)
+            d1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": m / d1, "unit": "boxes/s", "sample": "%d boxes, %.1f s" % (m, d1)}
+    return out
 
 
 def progress(msg):
@@ -399,6 +414,7 @@ def main():
         "config": {"workload": "3->256x8->1 ReLU closed-blob MLP (random init), %d boxes, half-widths "
                                "log-uniform [1e-4, 0.5], affine-truncate k=%d, classify" % (args.boxes, K_KEEP),
                    "boxes": args.boxes, "k": K_KEEP, "hidden": "256x8", "policy": "truncate",
+                   "bound": "rigorous (every rounding bounded, the library default)",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
@@ -412,12 +428,22 @@ def main():
         extra = {}
         which = set(args.extras.split(","))
         if "octree" in which:
+            # depth 10 in the paper's arithmetic (rounding ignored, as in the
+            # paper); with the rounding bound the frontier of this net grows
+            # past the 64M-cell cap at depth 10 (the FP32 rounding bound
+            # dominates the width of its smallest cells), so the rigorous tree
+            # is measured to depth 8
             t = time.perf_counter()
-            levels, leaves = spk.build_octree(ctx, g, 10, "truncate", K_KEEP)
+            levels, leaves = spk.build_octree(ctx, g, 10, "truncate", K_KEEP, rigorous=False)
             torch.cuda.synchronize()
             extra["octree_depth10_s"] = time.perf_counter() - t
             extra["octree_leaves"] = int(leaves.shape[0])
             extra["octree_frontier"] = [lv["n"] for lv in levels]
+            t = time.perf_counter()
+            levels, leaves = spk.build_octree(ctx, g, 8, "truncate", K_KEEP)
+            torch.cuda.synchronize()
+            extra["octree_rigorous_depth8_s"] = time.perf_counter() - t
+            extra["octree_rigorous_frontier"] = [lv["n"] for lv in levels]
             progress("octree done")
         if "rays" in which:
             extra["rays"] = rays_extra(ctx, g, dev)

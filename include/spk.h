@@ -80,8 +80,16 @@ typedef enum { SPK_AFFINE_FIXED = 0, SPK_AFFINE_TRUNCATE = 1, SPK_AFFINE_FULL = 
  *                  radius bounds the dropped lo*lo term, the W split
  *                  residual (measured exactly at network creation), the X
  *                  split residual, FP16 underflow and the accumulation.
- *                  Same restrictions as SPK_PREC_BF16X3. */
-typedef enum { SPK_PREC_F32 = 0, SPK_PREC_BF16X3 = 1, SPK_PREC_F16X3 = 2 } spk_prec;
+ *                  Same restrictions as SPK_PREC_BF16X3.
+ *  SPK_PREC_F64    generator products on the FP64 MFMA (16x16x4, W and X
+ *                  widened exactly from FP32), FP64 accumulation, the center
+ *                  column in FP64 through the same MFMA; results stored in
+ *                  FP32.  With the rounding bound this keeps the enclosure
+ *                  close to the exact affine bound also on the smallest boxes
+ *                  of deep networks, at about twice the matrix-core time of
+ *                  FP32.  Hidden width 256 only (else SPK_E_UNSUPPORTED);
+ *                  single-network bound calls only. */
+typedef enum { SPK_PREC_F32 = 0, SPK_PREC_BF16X3 = 1, SPK_PREC_F16X3 = 2, SPK_PREC_F64 = 3 } spk_prec;
 
 /* uint8 sign classes of Procedure 1. */
 enum { SPK_UNKNOWN = 0, SPK_POSITIVE = 1, SPK_NEGATIVE = 2 };

@@ -35,6 +35,28 @@ def forward(net, x):
     return h[:, 0]
 
 
+def forward_torch(net, x, threads=None):
+    """The same point evaluation as :func:`forward`, with PyTorch FP64 CPU
+    operations (multi-threaded matrix products and activations), for large
+    sample sets.  Returns a NumPy array [n]."""
+    import torch
+    if threads:
+        torch.set_num_threads(int(threads))
+    Ws, bs = _w(net)
+    h = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+    L = len(Ws)
+    for l in range(L):
+        h = torch.addmm(torch.from_numpy(bs[l]), h, torch.from_numpy(Ws[l]).T)
+        if l < L - 1:
+            if net.act == "sin":
+                h = torch.sin(net.omega0 * h)
+            elif net.act == "elu":
+                h = torch.where(h > 0, h, torch.expm1(torch.clamp(h, max=0.0)))
+            else:
+                h = torch.clamp(h, min=0.0)
+    return h[:, 0].numpy()
+
+
 def propagate(net, x0, X, xinf, policy="truncate", k=31, keep_sets=None, record=None):
     """Push an affine form through the network (Section 3 rules; Appendix A).
 

@@ -72,8 +72,10 @@ __device__ __forceinline__ float round_up_f(double v) {
 //    the evaluation error of (alpha, beta, gamma) go into yinf;
 //  * condensed sums are rounded upwards;
 //  * last, yinf receives u = cK r + cD |x0|, the a-priori rounding of the next
-//    layer's products (generators in FP32 or split precision against W, the
-//    center in FP64): that layer's |W| yinf then carries it.
+//    layer's products (generators in FP32, split precision or FP64 against W,
+//    the center in FP64): that layer's |W| yinf then carries it; generators
+//    produced in FP64 and stored in FP32 add uY times their stored magnitude
+//    before the range is read off.
 //
 // With `sent` non-null (first activation of a bound pass, truncate), every
 // kept new term placed in a slot C >= 4 is also recorded as the single entry
@@ -82,7 +84,7 @@ __device__ __forceinline__ float round_up_f(double v) {
 template <class S, int ACT, int POL, int NPASS>
 __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (&yinf)[4], float (&e)[4],
                                         float (&u)[4], int n_occ, int k, float cK, float cD, float omega0, int lane,
-                                        int16_t* rec, float* sent = nullptr, bool rig = false) {
+                                        int16_t* rec, float* sent = nullptr, bool rig = false, float uY = 0.0f) {
   static_assert(NPASS == 0 || POL == SPK_AFFINE_FIXED, "passengers ride along affine-fixed passes only");
   constexpr int NG = S::NS - NPASS;   // slots 1..NG-1 are generators
   float gam[4], rnext[4];
@@ -118,6 +120,9 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
     double rYd = 0.0;
 #pragma unroll
     for (int C = 1; C < NG; ++C) rYd += (double)fabsf(y[C][i]);
+    // rigorous: generators produced in FP64 and stored in FP32 are within uY
+    // of their stored magnitude; the range must cover the exact values
+    if (rig && uY > 0.0f) yinf[i] = round_up_f((double)yinf[i] + (double)uY * rYd * (1.0 + (double)(NG + 2) * kU64));
     double rd = rYd + (double)yinf[i];
     // rigorous: an FP64 sum of NG terms is within (NG + 1) 2^-53 of exact
     if (rig) rd = rd * (1.0 + (double)(NG + 2) * kU64) + (double)kEta;
@@ -677,6 +682,74 @@ __device__ __forceinline__ float single_box_pass_f16(LdsState<S>& sm, const f4* 
   return ssum;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Column tile n of the wave's single box (H = 256) with FP64 generator
+// products: the 16x16x4 FP64 MFMA in the same fragment order as the FP32 one
+// (lane (g, c) feeds W[16t' + c][16t + 4g + j] and X[16t + 4g + j][16n + c],
+// both widened exactly from FP32) with FP64 accumulation (the operands use
+// the FP32 MFMA's lane layout, the accumulators another one, see below); the
+// results are rounded to FP32 in the tile.  In tile 0 the lanes of column 0 feed the FP64
+// center x0 from sm.vc instead of its FP32 copy, so the center W x0 comes out
+// of the same MFMA in FP64 (column 0) and no VALU center sweep is needed;
+// |W| xinf (VA_CENTER) runs on VALU beside it.
+template <class S, int VA>
+__device__ __forceinline__ void single_box_pass_f64(LdsState<S>& sm, const f4* Wl, int n, int lane) {
+  constexpr int MT = S::MT, PF = 8;
+  static_assert(S::BPW == 1 && MT % PF == 0, "one box per wave; the ring index repeats every K block");
+  const int g = lane >> 4, c = lane & 15;
+  const bool ctr = (n == 0) && (c == 0);
+  d4 acc[MT];
+  float px[MT];
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    acc[tp] = (d4){0.0, 0.0, 0.0, 0.0};
+    px[tp] = 0.0f;
+  }
+  const f4* Wq = Wl + lane;
+  f4 ring[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) ring[p] = Wq[p * 64];
+#pragma unroll 1
+  for (int t = 0; t < MT; ++t) {
+    const f4 bfr = *(const f4*)&sm.tile[taddr<S>(0, 16 * n + c, 4 * t + g)];
+    double bd[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bd[j] = ctr ? sm.vc[16 * t + 4 * g + j] : (double)bfr[j];
+    f4 vx = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (VA != VA_NONE) vx = *(const f4*)&sm.vinf[16 * t + 4 * g];
+#pragma unroll
+    for (int tp = 0; tp < MT; ++tp) {
+      const f4 w = ring[tp % PF];
+      const int qn = min(t * MT + tp + PF, MT * MT - 1);   // past the end: a harmless reload
+      ring[tp % PF] = Wq[(size_t)qn * 64];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[tp] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)w[j], bd[j], acc[tp], 0, 0, 0);
+        if (VA != VA_NONE) px[tp] = fmaf(fabsf(w[j]), vx[j], px[tp]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tp = 0; tp < MT; ++tp) {
+    if (VA != VA_NONE) {
+      float sx = px[tp];
+      sx += __shfl_xor(sx, 16, 64);
+      sx += __shfl_xor(sx, 32, 64);
+      if (g == 0) sm.vinf[16 * tp + c] = sx;
+    }
+    // the FP64 MFMA's accumulator layout differs from the FP32 one (measured):
+    // lane (g, c) holds rows 16 tp + g + 4 i (i = 0..3) of column c
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (ctr) sm.vc[16 * tp + g + 4 * i] = acc[tp][i];
+      sm.tile[taddr<S>(0, 16 * n + c, 4 * tp + i) + g] = (float)acc[tp][i];
+    }
+  }
+  __syncthreads();
+}
+
 // Column tile n of every box of the wave (H < 256: several boxes) through one
 // H -> H layer.  This K block's A fragments are held for every output tile
 // (MT is small here) and reused box after box.
@@ -788,6 +861,11 @@ __device__ __forceinline__ void hidden_layer(const NetDev& net, LdsState<S>& sm,
     single_box_pass_split<S, VA_CENTER>(sm, Wl, Wbl, 0, lane);
 #pragma unroll 1
     for (int n = 1; n < NT; ++n) single_box_pass_split<S, VA_NONE>(sm, Wl, Wbl, n, lane);
+  } else if constexpr (PREC == SPK_PREC_F64) {
+    static_assert(BPW == 1, "FP64 products are built for one box per wave");
+    single_box_pass_f64<S, VA_CENTER>(sm, Wl, 0, lane);
+#pragma unroll 1
+    for (int n = 1; n < NT; ++n) single_box_pass_f64<S, VA_NONE>(sm, Wl, n, lane);
   } else if constexpr (BPW == 1 && NT == 2) {
     single_box_pass2<S, VA_CENTER>(sm, Wl, lane);
   } else if constexpr (BPW == 1) {

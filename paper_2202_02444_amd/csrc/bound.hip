@@ -90,11 +90,15 @@ static hipError_t launch_h(const NetDev& net, const BoundJob& job, hipStream_t s
 spk_status launch_bound(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus) {
   if (job.n <= 0) return SPK_OK;
   hipError_t err;
-  if (job.prec == SPK_PREC_BF16X3 || job.prec == SPK_PREC_F16X3) {
-    // split products are built for one box per wave (hidden width 256)
+  if (job.prec == SPK_PREC_BF16X3 || job.prec == SPK_PREC_F16X3 || job.prec == SPK_PREC_F64) {
+    // split and FP64 products are built for one box per wave (hidden width 256)
     if (net->dev.H != 256) return SPK_E_UNSUPPORTED;
-    err = job.prec == SPK_PREC_BF16X3 ? launch_h<256, SPK_PREC_BF16X3>(net->dev, job, stream, num_cus)
-                                      : launch_h<256, SPK_PREC_F16X3>(net->dev, job, stream, num_cus);
+    if (job.prec == SPK_PREC_BF16X3)
+      err = launch_h<256, SPK_PREC_BF16X3>(net->dev, job, stream, num_cus);
+    else if (job.prec == SPK_PREC_F16X3)
+      err = launch_h<256, SPK_PREC_F16X3>(net->dev, job, stream, num_cus);
+    else
+      err = launch_h<256, SPK_PREC_F64>(net->dev, job, stream, num_cus);
     return err == hipSuccess ? SPK_OK : SPK_E_DEVICE;
   }
   switch (net->dev.H) {

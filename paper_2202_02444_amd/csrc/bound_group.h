@@ -74,7 +74,11 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
   int n_occ = job.s;
   const bool rig = job.rigorous != 0;
   // the next layer's generator products: FP32 or split-BF16 rounding bound
-  const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs : (PREC == SPK_PREC_F16X3 ? net.cKh : net.cK);
+  // (FP64 products: the FP64 accumulation bound, and the FP32 rounding of
+  // each stored generator, relative to the stored value, folded by activate)
+  const float cKg = PREC == SPK_PREC_BF16X3 ? net.cKs
+                    : (PREC == SPK_PREC_F16X3 ? net.cKh : (PREC == SPK_PREC_F64 ? net.cD : net.cK));
+  const float uY = PREC == SPK_PREC_F64 ? kU * kGrow : 0.0f;
   if constexpr (S::BPW == 1) {
     {
       // first activation; with a hidden H -> H layer after it, that layer's
@@ -83,7 +87,7 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
       int16_t* rec = (job.slot_src != nullptr && valid) ? job.slot_src + (size_t)box * 32 : nullptr;
       float* sent = POL == SPK_AFFINE_TRUNCATE ? first_layer_sent<S>(sm, bo) : nullptr;
       n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec, sent,
-                                       rig);
+                                       rig, 0.0f);
     }
     if (L > 2) {
       const int klast = POL == SPK_AFFINE_TRUNCATE ? job.k : 3;
@@ -95,7 +99,7 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
         int16_t* rec = nullptr;
         if (job.slot_src != nullptr && valid) rec = job.slot_src + ((size_t)a * job.n + box) * 32;
         n_occ = activate<S, ACT, POL, 0>(xc, y, yinf, e, u, n_occ, job.k, cKg, net.cD, net.omega0, lane, rec,
-                                       nullptr, rig);
+                                         nullptr, rig, uY);
         if (a == L - 2) break;
         hidden_layer<S, 0, PREC>(net, sm, a, xc, y, yinf, e, u, lane, job.rigorous != 0);
       }

@@ -134,13 +134,14 @@ inline bool rigorous_opts(const spk_bound_opts* o) { return (o->flags & SPK_FLAG
 
 inline spk_status valid_opts(const spk_bound_opts* o) {
   if (o == nullptr) return SPK_E_INVAL;
-  if (o->prec != SPK_PREC_F32 && o->prec != SPK_PREC_BF16X3 && o->prec != SPK_PREC_F16X3) return SPK_E_UNSUPPORTED;
+  if (o->prec != SPK_PREC_F32 && o->prec != SPK_PREC_BF16X3 && o->prec != SPK_PREC_F16X3 && o->prec != SPK_PREC_F64)
+    return SPK_E_UNSUPPORTED;
   if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
   if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
   if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;
   if (o->flags & ~(uint32_t)(SPK_FLAG_RIGOROUS | SPK_FLAG_NO_ROUNDING_BOUND)) return SPK_E_INVAL;
   if (o->flags & SPK_FLAG_NO_ROUNDING_BOUND) {
-    if ((o->flags & SPK_FLAG_RIGOROUS) || o->prec != SPK_PREC_F32) return SPK_E_INVAL;
+    if ((o->flags & SPK_FLAG_RIGOROUS) || o->prec == SPK_PREC_BF16X3 || o->prec == SPK_PREC_F16X3) return SPK_E_INVAL;
   }
   return SPK_OK;
 }

@@ -161,7 +161,7 @@ FLAG_RIGOROUS = 1
 FLAG_NO_ROUNDING_BOUND = 2
 
 
-PREC = {"f32": 0, "bf16x3": 1, "f16x3": 2}
+PREC = {"f32": 0, "bf16x3": 1, "f16x3": 2, "f64": 3}
 
 
 def opts(policy="truncate", k=31, rigorous=True, prec="f32"):

@@ -195,3 +195,52 @@ def test_full_size_split_precision_sampled(ctx, prec):
     assert np.all(e > 0) and np.all(np.isfinite(c)) and np.all(r >= 0)
     bad, _ = soundness_violations(net, lo[idx], hi[idx], g_lo, g_hi, np.random.default_rng(22))
     assert bad == 0
+
+
+def test_precision_soundness_1e7_points(ctx):
+    """The precision workload (the 8x256 blob, 1M boxes, truncate k = 31) in
+    FP32, split BF16 and split FP16, all with the rounding bound: 10 seeded
+    uniform points in every box (10,485,760 points) plus the 8 corners of
+    100,000 boxes, f evaluated in FP64 on the host, lie inside every
+    precision's bound."""
+    import time
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.scale_net(1)
+    g = spk.Net.from_spec(net)
+    lo, hi = wl.boxes(N_FULL, 11, 1e-4, 0.5)
+    dev = torch.device("cuda")
+    tl, th = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
+    bounds = {}
+    for prec in ("f32", "bf16x3", "f16x3"):
+        lab = torch.empty(N_FULL, dtype=torch.uint8, device=dev)
+        glo = torch.empty(N_FULL, device=dev)
+        ghi = torch.empty(N_FULL, device=dev)
+        spk.classify_boxes(ctx, g, tl, th, lab, glo, ghi, "truncate", 31, prec=prec)
+        ctx.sync()
+        bounds[prec] = (glo.cpu().numpy().astype(np.float64), ghi.cpu().numpy().astype(np.float64))
+    lo64, hi64 = lo.astype(np.float64), hi.astype(np.float64)
+    rng = np.random.default_rng(2025)
+    chunk = 1 << 15
+    n_pts = 0
+    t0 = time.perf_counter()
+    for b0 in range(0, N_FULL, chunk):
+        b1 = min(b0 + chunk, N_FULL)
+        t = rng.uniform(0.0, 1.0, (b1 - b0, 10, 3))
+        P = lo64[b0:b1, None, :] + t * (hi64[b0:b1] - lo64[b0:b1])[:, None, :]
+        f = omlp.forward_torch(net, P.reshape(-1, 3)).reshape(b1 - b0, 10)
+        n_pts += f.size
+        for prec, (glo, ghi) in bounds.items():
+            bad = (f < glo[b0:b1, None]) | (f > ghi[b0:b1, None])
+            assert not bad.any(), (prec, b0 + int(np.flatnonzero(bad.any(axis=1))[0]))
+        if (b0 // chunk) % 8 == 0:
+            print("soundness: %d points checked (%.0f s)" % (n_pts, time.perf_counter() - t0), flush=True)
+    idx = rng.choice(N_FULL, 100000, replace=False)
+    corners = np.array(np.meshgrid([0, 1], [0, 1], [0, 1], indexing="ij")).reshape(3, -1).T.astype(np.float64)
+    P = lo64[idx, None, :] + corners[None] * (hi64[idx] - lo64[idx])[:, None, :]
+    f = omlp.forward_torch(net, P.reshape(-1, 3)).reshape(len(idx), 8)
+    for prec, (glo, ghi) in bounds.items():
+        assert not ((f < glo[idx, None]) | (f > ghi[idx, None])).any(), prec
+    print("soundness: %d random points and %d corners inside the FP32, BF16 and FP16 bounds (%.0f s)" % (
+        n_pts, f.size, time.perf_counter() - t0), flush=True)
+    assert n_pts >= 10_000_000

@@ -31,7 +31,7 @@ NETS = {"blob": lambda: wl.scale_net(1),
         "sin3": lambda: wl.siren_mlp([3] + [256] * 3 + [1], 63, 30.0)}
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3", "f64"])
 @pytest.mark.parametrize("name", list(NETS))
 @pytest.mark.parametrize("policy,k", [("truncate", 31), ("truncate", 15), ("fixed", 0)])
 def test_split_encloses_oracle(ctx, prec, name, policy, k):
@@ -120,7 +120,7 @@ def test_split_f16_extreme_scales(ctx):
             assert bad == 0
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
+@pytest.mark.parametrize("prec", ["bf16x3", "f16x3", "f64"])
 def test_split_unsupported_shapes(ctx, prec):
     import torch
     from paper_2202_02444_amd import spk
@@ -140,3 +140,34 @@ def test_split_unsupported_shapes(ctx, prec):
                            items[0]["box_hi"].data_ptr(), items[0]["label"].data_ptr(), None, None)
     h = ctypes.c_void_p()
     assert spk.lib().spk_batch_create(ctx.handle, ctypes.byref(o), 1, arr, ctypes.byref(h)) == spk.E_UNSUPPORTED
+
+
+def test_f64_products_tight_and_in_parity(ctx):
+    """FP64 generator products on the blob sample: with the rounding bound the
+    enclosure stays close to the oracle's exact bound also on the smallest
+    boxes (the FP32 products' a-priori rounding dominates those), and in the
+    paper's arithmetic the raw endpoints match the oracle within TOL."""
+    from paper_2202_02444_amd import spk
+    from parity import endpoint_errors
+    net = wl.scale_net(1)
+    g = spk.Net.from_spec(net)
+    lo, hi = wl.boxes(1024, 11, 1e-4, 0.5)
+    for rig in (True, False):
+        out = gpu_classify(ctx, g, lo, hi, "truncate", 31, want_src=True, rigorous=rig, prec="f64")
+        sets = keep_sets_from_src(out["src"], 3, 31, 256)
+        _, _, lo_o, hi_o = omlp.bound_boxes(net, lo, hi, "truncate", 31, keep_sets=sets)
+        S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+        if rig:
+            viol, ratio = rigorous_vs_oracle(out, lo_o, hi_o, S)
+            lab_o = np.where(lo_o > 0, 1, np.where(hi_o < 0, 2, 0))
+            kept = np.mean(out["label"][lab_o != 0] == lab_o[lab_o != 0])
+            print("f64 rigorous blob: containment %.2e, width ratio median %.4f p90 %.3g p99 %.3g, oracle labels "
+                  "kept %.3f" % (viol.max(), np.median(ratio), np.quantile(ratio, 0.9), np.quantile(ratio, 0.99), kept))
+            assert viol.max() <= TOL
+            assert np.median(ratio) <= 1.01 and kept >= 0.5
+            bad, _ = soundness_violations(net, lo, hi, out["lo"], out["hi"], np.random.default_rng(66))
+            assert bad == 0
+        else:
+            e = endpoint_errors(out["center"], out["radius"], lo_o, hi_o, S)
+            print("f64 paper arithmetic blob: max endpoint error %.3e" % e.max())
+            assert e.max() <= TOL

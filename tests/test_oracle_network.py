@@ -245,3 +245,19 @@ def test_rotated_box_equals_aabb_when_axes_are_diagonal():
     ly, hy = mlp.bound_general(net, c, axes, "truncate", 7)
     _, _, la, ha = mlp.bound_boxes(net, c - h, c + h, "truncate", 7)
     assert np.allclose(ly, la, rtol=1e-13, atol=1e-13) and np.allclose(hy, ha, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["relu", "elu", "sin", "blob"])
+def test_forward_torch_equals_forward(name):
+    """The PyTorch FP64 point evaluation (used for large soundness samples)
+    equals the NumPy one to FP64 rounding."""
+    import workloads as wl
+    from oracle import mlp as omlp
+    net = {"relu": lambda: wl.he_normal_mlp([3, 64, 64, 1], 5),
+           "elu": lambda: wl.he_normal_mlp([3, 64, 64, 64, 1], 6, act="elu"),
+           "sin": lambda: wl.siren_mlp([3, 32, 32, 1], 7, 30.0),
+           "blob": lambda: wl.scale_net(1)}[name]()
+    x = np.random.default_rng(3).uniform(-1.2, 1.2, (2000, 3))
+    a = omlp.forward(net, x)
+    b = omlp.forward_torch(net, x)
+    assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(a)))
