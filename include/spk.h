@@ -134,6 +134,11 @@ const char* spk_version(void);
  */
 spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* const* W,
                           const float* const* b, int32_t act, float omega0, spk_net** out);
+/* Frees the network.  SPK_E_BUSY (nothing freed) while a batch or a server
+ * still references it, or while work launched on it by a bound, frontier,
+ * ray, closest-point or evaluation call has not finished on its stream (the
+ * non-allocating frontier call and calls made under HIP graph capture are
+ * not tracked: the caller orders those). */
 spk_status spk_net_destroy(spk_net* net);
 
 /*
@@ -143,8 +148,24 @@ spk_status spk_net_destroy(spk_net* net);
  */
 spk_status spk_ctx_create(void* stream, size_t workspace_bytes, spk_ctx** out);
 spk_status spk_ctx_destroy(spk_ctx* ctx);
-/* Wait for all work of the context's stream. */
-spk_status spk_ctx_sync(spk_ctx* ctx);
+
+/* Device-side conditions of the context's calls since the previous
+ * spk_ctx_sync (the kernels write them; spk_ctx_sync reads and clears them). */
+typedef struct {
+  int64_t nonfinite_inputs;  /* boxes whose input coordinates were not all finite
+                                (their results are [-inf, +inf], UNKNOWN)       */
+  int32_t nospc;             /* 1: a frontier round found more children or
+                                leaves than its capacity                        */
+  int32_t reserved;
+  int64_t need_children;     /* largest required capacities among those rounds  */
+  int64_t need_leaves;
+} spk_device_status;
+
+/* Wait for all work of the context's stream and read the device status word.
+ * status (host, nullable) receives it.  Returns SPK_E_NOSPC when a frontier
+ * round overflowed a capacity since the previous sync (the counts of that
+ * round hold its required sizes), else the stream's status. */
+spk_status spk_ctx_sync(spk_ctx* ctx, spk_device_status* status);
 
 /*
  * Optional diagnostic outputs of the bound calls (all dev, nullable).
@@ -210,8 +231,8 @@ typedef struct {
  *   counts   dev int64 [4]: n_children, n_leaves, n_pos, n_neg.  The call sets
  *            them (it does not accumulate).  Output order is unspecified.
  * When a capacity is too small the required count is still written to
- * `counts`, entries beyond the capacity are dropped, and spk_ctx_sync returns
- * nothing special: the caller compares counts with the capacities.
+ * `counts`, entries beyond the capacity are dropped, and the next
+ * spk_ctx_sync returns SPK_E_NOSPC with the required sizes in its status.
  */
 spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
                                   const spk_tree_params* tree, int32_t level, const uint64_t* cells,

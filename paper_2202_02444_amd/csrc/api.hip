@@ -138,6 +138,22 @@ static spk_status noalloc_scratch(int device, void** p) {
   return SPK_OK;
 }
 
+namespace spk {
+void net_mark_use(const spk_net* net, hipStream_t stream) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
+  std::lock_guard<std::mutex> lock(net->use_mu);
+  hipEvent_t ev = nullptr;
+  for (auto& u : net->uses)
+    if (u.first == stream) ev = u.second;
+  if (ev == nullptr) {
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
+    net->uses.emplace_back(stream, ev);
+  }
+  (void)hipEventRecord(ev, stream);
+}
+}  // namespace spk
+
 extern "C" {
 
 const char* spk_status_str(spk_status s) {
@@ -355,6 +371,14 @@ spk_status spk_net_create(int32_t n_linear, const int32_t* widths, const float* 
 
 spk_status spk_net_destroy(spk_net* net) {
   if (net == nullptr) return SPK_E_INVAL;
+  if (net->holders.load() > 0) return SPK_E_BUSY;
+  {
+    std::lock_guard<std::mutex> lock(net->use_mu);
+    for (auto& u : net->uses)
+      if (hipEventQuery(u.second) == hipErrorNotReady) return SPK_E_BUSY;
+    for (auto& u : net->uses) (void)hipEventDestroy(u.second);
+    net->uses.clear();
+  }
   spk_status st = SPK_OK;
   if (net->dev_block) st = check_hip(hipFree(net->dev_block));
   delete net;
@@ -370,8 +394,18 @@ spk_status spk_ctx_create(void* stream, size_t workspace_bytes, spk_ctx** out) {
   ctx->workspace_limit = workspace_bytes;
   ctx->scratch = nullptr;
   ctx->scratch_bytes = 0;
+  ctx->status = nullptr;
   if (hipGetDevice(&ctx->device) != hipSuccess ||
       hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
+    delete ctx;
+    return SPK_E_DEVICE;
+  }
+  if (hipMalloc(&ctx->status, 256) != hipSuccess) {
+    delete ctx;
+    return SPK_E_NOMEM;
+  }
+  if (hipMemset(ctx->status, 0, 256) != hipSuccess) {
+    (void)hipFree(ctx->status);
     delete ctx;
     return SPK_E_DEVICE;
   }
@@ -381,18 +415,22 @@ spk_status spk_ctx_create(void* stream, size_t workspace_bytes, spk_ctx** out) {
 
 spk_status spk_ctx_destroy(spk_ctx* ctx) {
   if (ctx == nullptr) return SPK_E_INVAL;
-  spk_status st = SPK_OK;
-  if (ctx->scratch) {
-    st = check_hip(hipStreamSynchronize(ctx->stream));
-    if (hipFree(ctx->scratch) != hipSuccess) st = SPK_E_DEVICE;
-  }
+  spk_status st = check_hip(hipStreamSynchronize(ctx->stream));
+  if (ctx->scratch && hipFree(ctx->scratch) != hipSuccess) st = SPK_E_DEVICE;
+  if (ctx->status && hipFree(ctx->status) != hipSuccess) st = SPK_E_DEVICE;
   delete ctx;
   return st;
 }
 
-spk_status spk_ctx_sync(spk_ctx* ctx) {
+spk_status spk_ctx_sync(spk_ctx* ctx, spk_device_status* status) {
   if (ctx == nullptr) return SPK_E_INVAL;
-  return check_hip(hipStreamSynchronize(ctx->stream));
+  spk_status st = check_hip(hipStreamSynchronize(ctx->stream));
+  if (st != SPK_OK) return st;
+  spk_device_status ds = {};
+  if (hipMemcpy(&ds, ctx->status, sizeof(ds), hipMemcpyDeviceToHost) != hipSuccess) return SPK_E_DEVICE;
+  if (hipMemset(ctx->status, 0, sizeof(ds)) != hipSuccess) return SPK_E_DEVICE;
+  if (status != nullptr) *status = ds;
+  return ds.nospc ? SPK_E_NOSPC : SPK_OK;
 }
 
 static spk_status ctx_scratch(spk_ctx* ctx, size_t bytes, void** p) {
@@ -442,8 +480,11 @@ spk_status spk_range_bound(spk_ctx* ctx, const spk_net* net, const spk_bound_opt
   job.b = axes;
   job.lo = lo;
   job.hi = hi;
+  job.nonfinite = (unsigned long long*)ctx->status;
   fill_aux(job, aux);
-  return launch_bound(net, job, ctx->stream, ctx->num_cus);
+  st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+  if (st == SPK_OK) net_mark_use(net, ctx->stream);
+  return st;
 }
 
 spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n,
@@ -469,8 +510,11 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
   job.lo = lo;
   job.hi = hi;
   job.label = label;
+  job.nonfinite = (unsigned long long*)ctx->status;
   fill_aux(job, aux);
-  return launch_bound(net, job, ctx->stream, ctx->num_cus);
+  st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+  if (st == SPK_OK) net_mark_use(net, ctx->stream);
+  return st;
 }
 
 // One frontier round given the per-cell label buffer `labels` (n bytes of
@@ -494,12 +538,13 @@ static spk_status subdivide_round(spk_ctx* ctx, const spk_net* net, const spk_bo
     job.dom_hi[d] = tree->dom_hi[d];
   }
   job.label = labels;
+  job.nonfinite = (unsigned long long*)ctx->status;
   if (n > 0) {
     spk_status st = launch_bound(net, job, ctx->stream, ctx->num_cus);
     if (st != SPK_OK) return st;
   }
   return launch_compact(labels, cells, n, level == tree->max_level, children, cap_children, leaves, cap_leaves,
-                        counts, ctx->stream, ctx->num_cus);
+                        counts, ctx->status, ctx->stream, ctx->num_cus);
 }
 
 static spk_status check_subdivide_args(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
@@ -532,8 +577,10 @@ spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bo
     st = ctx_scratch(ctx, (size_t)n, &labels);
     if (st != SPK_OK) return st;
   }
-  return subdivide_round(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves, cap_leaves, counts,
-                         (uint8_t*)labels);
+  st = subdivide_round(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves, cap_leaves, counts,
+                       (uint8_t*)labels);
+  if (st == SPK_OK) net_mark_use(net, ctx->stream);
+  return st;
 }
 
 spk_status spk_subdivide_frontier_noalloc(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
@@ -566,7 +613,9 @@ spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params*
   void* counter = nullptr;
   spk_status st = ctx_scratch(ctx, 256, &counter);
   if (st != SPK_OK) return st;
-  return launch_rays(net, p, n, origin, dir, t_hit, iters, (unsigned long long*)counter, ctx->stream, ctx->num_cus);
+  st = launch_rays(net, p, n, origin, dir, t_hit, iters, (unsigned long long*)counter, ctx->stream, ctx->num_cus);
+  if (st == SPK_OK) net_mark_use(net, ctx->stream);
+  return st;
 }
 
 namespace {
@@ -669,7 +718,7 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
     job.policy = opts->policy;
     job.k = opts->k;
     job.prec = opts->prec;
-  job.rigorous = rigorous_opts(opts) ? 1 : 0;
+    job.rigorous = rigorous_opts(opts) ? 1 : 0;
     job.cells = (const uint64_t*)codes;
     job.level = level;
     for (int d = 0; d < 3; ++d) {
@@ -677,6 +726,7 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
       job.dom_hi[d] = tree->dom_hi[d];
     }
     job.label = (uint8_t*)labels;
+    job.nonfinite = (unsigned long long*)ctx->status;
     st = launch_bound(net, job, ctx->stream, ctx->num_cus);
     if (st != SPK_OK) return st;
     CpLevel L = {};
@@ -757,7 +807,9 @@ spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const fl
   if (ctx == nullptr || net == nullptr || n < 0) return SPK_E_INVAL;
   if (n == 0) return SPK_OK;
   if (x == nullptr || f == nullptr) return SPK_E_INVAL;
-  return launch_eval(net, n, x, f, ctx->stream, ctx->num_cus);
+  const spk_status st = launch_eval(net, n, x, f, ctx->stream, ctx->num_cus);
+  if (st == SPK_OK) net_mark_use(net, ctx->stream);
+  return st;
 }
 
 }  // extern "C"

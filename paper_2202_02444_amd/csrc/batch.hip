@@ -133,6 +133,8 @@ struct spk_batch {
   std::vector<hipEvent_t> ev;
   bool concurrent = true;          // class kernels as parallel graph branches
   float graph_ms = 0.0f;           // tuned time of one graph launch
+  hipEvent_t last = nullptr;       // recorded after every spk_batch_launch
+  bool held = false;               // the batch counts as a holder of its networks
 };
 
 namespace {
@@ -314,10 +316,13 @@ spk_status spk_batch_create(spk_ctx* ctx, const spk_bound_opts* opts, int32_t n_
   st = write_descriptors(b, items, ctx->stream);
   for (ClassPlan& p : b->classes) p.blocks = default_blocks(b, p);
   if (st == SPK_OK) st = capture(b);
+  if (st == SPK_OK && hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess) st = SPK_E_DEVICE;
   if (st != SPK_OK) {
     spk_batch_destroy(b);
     return st;
   }
+  for (const spk_net* n : b->nets) n->holders.fetch_add(1);
+  b->held = true;
   *out = b;
   return SPK_OK;
 }
@@ -334,7 +339,8 @@ spk_status spk_batch_update(spk_ctx* ctx, spk_batch* b, int32_t n_items, const s
 
 spk_status spk_batch_launch(spk_ctx* ctx, spk_batch* b) {
   if (ctx == nullptr || b == nullptr || b->exec == nullptr) return SPK_E_INVAL;
-  return hipGraphLaunch(b->exec, ctx->stream) == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+  if (hipGraphLaunch(b->exec, ctx->stream) != hipSuccess) return SPK_E_DEVICE;
+  return hipEventRecord(b->last, ctx->stream) == hipSuccess ? SPK_OK : SPK_E_DEVICE;
 }
 
 // Launch-shape autotuner: for every class, time each candidate (persistent
@@ -438,6 +444,13 @@ spk_status spk_batch_classes(const spk_batch* b, int32_t* n_classes, spk_batch_c
 spk_status spk_batch_destroy(spk_batch* b) {
   if (b == nullptr) return SPK_E_INVAL;
   spk_status st = SPK_OK;
+  // the device buffers and the graph stay alive until the last launch ended
+  if (b->last) {
+    if (hipEventSynchronize(b->last) != hipSuccess) st = SPK_E_DEVICE;
+    (void)hipEventDestroy(b->last);
+  }
+  if (b->held)
+    for (const spk_net* n : b->nets) n->holders.fetch_sub(1);
   drop_graph(b);
   for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);

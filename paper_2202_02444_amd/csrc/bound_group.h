@@ -67,6 +67,17 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
   double cc[3];
   float ax[3][3], ein[3], pts[1][3] = {{0.0f, 0.0f, 0.0f}};
   box_input(job, box, valid, cc, ax, ein);
+  if (job.nonfinite != nullptr && valid && ch == 0) {
+    // device status: boxes whose input coordinates are not all finite
+    bool fin = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      fin = fin && isfinite(cc[d]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) fin = fin && isfinite(ax[q][d]);
+    }
+    if (!fin) atomicAdd(job.nonfinite, 1ull);
+  }
   double xc[4];
   f4 y[NS];
   float yinf[4], e[4], u[4] = {0.0f, 0.0f, 0.0f, 0.0f};

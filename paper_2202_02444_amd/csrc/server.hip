@@ -90,7 +90,7 @@ void worker_main(spk_server* s, spk_ctx* ctx) {
     }
     const double start = now_s();
     spk_status st = run_request(ctx, s, p.req);
-    if (st == SPK_OK) st = spk_ctx_sync(ctx);
+    if (st == SPK_OK) st = spk_ctx_sync(ctx, nullptr);
     const double end = now_s();
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -145,6 +145,7 @@ spk_status spk_server_create(const spk_net* const* nets, int32_t n_nets, size_t 
     delete s;
     return SPK_E_DEVICE;
   }
+  for (const spk_net* n : s->nets) n->holders.fetch_add(1);
   for (spk_ctx* c : ctxs) s->workers.emplace_back(worker_main, s, c);
   *out = s;
   return SPK_OK;
@@ -206,6 +207,7 @@ spk_status spk_server_destroy(spk_server* s) {
   s->cv_work.notify_all();
   for (std::thread& t : s->workers) t.join();
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  for (const spk_net* n : s->nets) n->holders.fetch_sub(1);
   delete s;
   return SPK_OK;
 }

@@ -4,6 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "spk.h"
 
 namespace spk {
@@ -66,6 +71,7 @@ struct BoundJob {
   float* radius;
   float* err;
   int16_t* slot_src;
+  unsigned long long* nonfinite;   // device status: boxes with non-finite inputs (nullable)
 };
 
 // FP32 bounds of the octree cell with Morton code `code` at `level` (bit b of
@@ -116,6 +122,11 @@ struct spk_net {
   int device;
   int32_t n_linear;
   int32_t width;
+  // batches and servers that reference the network
+  mutable std::atomic<int> holders{0};
+  // the last launch on the network per stream (spk_net_destroy checks them)
+  mutable std::mutex use_mu;
+  mutable std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 struct spk_ctx {
@@ -126,6 +137,8 @@ struct spk_ctx {
   // scratch (grown on demand)
   void* scratch;
   size_t scratch_bytes;
+  // device status word (spk_device_status layout), cleared by spk_ctx_sync
+  void* status;
 };
 
 namespace spk {
@@ -146,11 +159,14 @@ inline spk_status valid_opts(const spk_bound_opts* o) {
   return SPK_OK;
 }
 
+// Records that work on `net` was enqueued on `stream` (for SPK_E_BUSY).
+void net_mark_use(const spk_net* net, hipStream_t stream);
+
 // Launch helpers implemented in bound.hip / tree.hip / rays.hip.
 spk_status launch_bound(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus);
 spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t n, bool at_max,
                           uint64_t* children, int64_t cap_children, uint64_t* leaves, int64_t cap_leaves,
-                          int64_t* counts, hipStream_t stream, int num_cus);
+                          int64_t* counts, void* status, hipStream_t stream, int num_cus);
 spk_status launch_eval(const spk_net* net, int64_t n, const float* x, float* f, hipStream_t stream,
                        int num_cus);
 spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, const float* origin,

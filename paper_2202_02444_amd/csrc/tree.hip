@@ -52,8 +52,22 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict_
   }
 }
 
+// Device status of a round (spk_device_status layout: nospc at byte 8, the
+// required capacities at bytes 16 and 24): one thread compares the round's
+// counts with its capacities after the compaction.
+__global__ void round_status_kernel(const unsigned long long* counts, int64_t cap_children, int64_t cap_leaves,
+                                    unsigned char* status) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long nc = counts[0], nl = counts[1];
+  if (nc > (unsigned long long)cap_children || nl > (unsigned long long)cap_leaves) {
+    *(int*)(status + 8) = 1;
+    atomicMax((unsigned long long*)(status + 16), nc);
+    atomicMax((unsigned long long*)(status + 24), nl);
+  }
+}
+
 spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t n, bool at_max, uint64_t* children,
-                          int64_t cap_children, uint64_t* leaves, int64_t cap_leaves, int64_t* counts,
+                          int64_t cap_children, uint64_t* leaves, int64_t cap_leaves, int64_t* counts, void* status,
                           hipStream_t stream, int num_cus) {
   hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, stream, (unsigned long long*)counts);
   if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
@@ -62,7 +76,13 @@ spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t 
   if (blocks > (int64_t)num_cus * 8) blocks = (int64_t)num_cus * 8;
   hipLaunchKernelGGL(compact_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, labels, cells, n, at_max ? 1 : 0,
                      children, cap_children, leaves, cap_leaves, (unsigned long long*)counts);
-  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+  if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
+  if (status != nullptr) {
+    hipLaunchKernelGGL(round_status_kernel, dim3(1), dim3(64), 0, stream, (const unsigned long long*)counts,
+                       cap_children, cap_leaves, (unsigned char*)status);
+    if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
+  }
+  return SPK_OK;
 }
 
 }  // namespace spk

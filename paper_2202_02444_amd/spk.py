@@ -61,6 +61,11 @@ class BoundAux(ctypes.Structure):
                 ("slot_src", ctypes.c_void_p)]
 
 
+class DeviceStatus(ctypes.Structure):
+    _fields_ = [("nonfinite_inputs", ctypes.c_int64), ("nospc", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("need_children", ctypes.c_int64), ("need_leaves", ctypes.c_int64)]
+
+
 class TreeParams(ctypes.Structure):
     _fields_ = [("dom_lo", ctypes.c_float * 3), ("dom_hi", ctypes.c_float * 3), ("max_level", ctypes.c_int32),
                 ("arity", ctypes.c_int32)]
@@ -99,7 +104,7 @@ def lib():
         L.spk_net_destroy.argtypes = [vp]
         L.spk_ctx_create.argtypes = [vp, sz, ctypes.POINTER(vp)]
         L.spk_ctx_destroy.argtypes = [vp]
-        L.spk_ctx_sync.argtypes = [vp]
+        L.spk_ctx_sync.argtypes = [vp, ctypes.POINTER(DeviceStatus)]
         L.spk_range_bound.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, i32, vp, vp, vp, vp,
                                       ctypes.POINTER(BoundAux)]
         L.spk_classify_boxes.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, vp, vp, vp, vp, vp,
@@ -218,8 +223,16 @@ class Context:
         _check(lib().spk_ctx_create(ctypes.c_void_p(stream), workspace_bytes, ctypes.byref(h)), "spk_ctx_create")
         self.handle = h
 
-    def sync(self):
-        _check(lib().spk_ctx_sync(self.handle), "spk_ctx_sync")
+    def sync(self, allow_nospc=False):
+        """Wait for the context's stream; return the device status word since
+        the previous sync as a dict.  A frontier overflow raises SpkError
+        (E_NOSPC) unless allow_nospc."""
+        ds = DeviceStatus()
+        st = lib().spk_ctx_sync(self.handle, ctypes.byref(ds))
+        if st != OK and not (st == E_NOSPC and allow_nospc):
+            raise SpkError(st, "spk_ctx_sync")
+        return {"nonfinite_inputs": int(ds.nonfinite_inputs), "nospc": bool(ds.nospc),
+                "need_children": int(ds.need_children), "need_leaves": int(ds.need_leaves)}
 
     def close(self):
         if self.handle:
@@ -490,12 +503,13 @@ def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 
         lv = torch.empty(max(capl, 1), dtype=torch.int64, device=dev)
         subdivide_frontier(ctx, net, level, cells, children[:capc] if capc else None, lv[:capl] if capl else None,
                            counts, max_level, policy, k, dom_lo, dom_hi, rigorous=rigorous)
+        ds = ctx.sync(allow_nospc=True)
         c = counts.cpu().tolist()
         levels.append({"level": level, "n": n, "n_children": c[0], "n_leaves": c[1], "n_pos": c[2], "n_neg": c[3]})
         if at_max:
             leaves = lv[:c[1]]
             break
-        if c[0] > capc:
+        if ds["nospc"] or c[0] > capc:
             raise SpkError(E_NOSPC, "build_octree")
         cells = children[:c[0]]
     return levels, leaves

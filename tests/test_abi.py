@@ -70,7 +70,7 @@ def test_bound_calls_validate_before_launch():
     full = spk.opts("full", 0)
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(full), 4, FAKE, FAKE, FAKE, None, None,
                                 None) == spk.E_UNSUPPORTED
-    badprec = spk.BoundOpts(1, 31, 3, 0)   # no spk_prec 3
+    badprec = spk.BoundOpts(1, 31, 4, 0)   # no spk_prec 4
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(badprec), 4, FAKE, FAKE, FAKE, None, None,
                                 None) == spk.E_UNSUPPORTED
     badflag = spk.BoundOpts(1, 31, 2, 2)   # unknown flag bit
@@ -88,6 +88,8 @@ def test_bound_calls_validate_before_launch():
     aux = spk.BoundAux(None, None, None, FAKE)
     assert L.spk_range_bound(FAKE, FAKE, ctypes.byref(fx), 4, 3, FAKE, FAKE, FAKE, FAKE,
                              ctypes.byref(aux)) == spk.E_INVAL
+    assert L.spk_ctx_sync(None, None) == spk.E_INVAL
+    assert L.spk_net_destroy(None) == spk.E_INVAL
 
 
 def test_tree_and_ray_validation():
@@ -171,7 +173,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {"spk_bound_opts": spk.BoundOpts, "spk_bound_aux": spk.BoundAux, "spk_tree_params": spk.TreeParams,
                "spk_ray_params": spk.RayParams, "spk_batch_item": spk.BatchItem, "spk_batch_class": spk.BatchClass,
-               "spk_request": spk.Request, "spk_completion": spk.Completion}
+               "spk_request": spk.Request, "spk_completion": spk.Completion,
+               "spk_device_status": spk.DeviceStatus}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "spk.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))

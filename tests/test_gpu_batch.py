@@ -145,3 +145,29 @@ def test_batch_vs_oracle(ctx, rigorous):
         bad, _ = soundness_violations(net, lo, hi, glo, ghi, np.random.default_rng(9))
         assert bad == 0, net.name
     b.close()
+
+
+def test_net_destroy_busy_while_held(ctx):
+    """spk_net_destroy refuses (SPK_E_BUSY, nothing freed) while a batch holds
+    the network, and frees it once the batch is gone."""
+    import torch
+    from paper_2202_02444_amd import spk
+    specs = [wl.tiny_net(0), wl.he_normal_mlp([3, 64, 64, 1], 54, act="relu")]
+    gnets = [spk.Net.from_spec(s) for s in specs]
+    items = _items(specs, gnets, [300, 500], 90)
+    b = spk.Batch(ctx, items, "truncate", 31)
+    b.launch(ctx)
+    ctx.sync()
+    lab0 = items[0]["label"].cpu().numpy().copy()
+    L = spk.lib()
+    assert L.spk_net_destroy(gnets[0].handle) == spk.E_BUSY
+    # the network still works
+    lab, _, _ = _single(ctx, items[0], "truncate", 31)
+    np.testing.assert_array_equal(lab, lab0)
+    b.launch(ctx)
+    ctx.sync()
+    np.testing.assert_array_equal(items[0]["label"].cpu().numpy(), lab0)
+    b.close()
+    gnets[0].close()                             # now frees
+    assert gnets[0].handle is None
+    gnets[1].close()

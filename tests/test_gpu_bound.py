@@ -129,6 +129,7 @@ def test_nonfinite_inputs(ctx):
     hi[5, 0] = np.inf
     lo[7, 2] = -np.inf
     g = spk.Net.from_spec(net)
+    ctx.sync()                                   # clears the status word
     out = gpu_classify(ctx, g, lo, hi, "truncate", 31)
     for i in (3, 5, 7):
         assert out["label"][i] == spk.UNKNOWN
@@ -136,6 +137,21 @@ def test_nonfinite_inputs(ctx):
     ok = np.ones(64, bool)
     ok[[3, 5, 7]] = False
     assert np.all(np.isfinite(out["lo"][ok]))
+    # the device status word counted the three boxes (gpu_classify synced once,
+    # which read and cleared it); a second launch counts them again
+    out = gpu_classify(ctx, g, lo, hi, "fixed", 0, rigorous=True)
+    st = ctx.sync()
+    assert st["nonfinite_inputs"] == 0 and not st["nospc"]
+    import torch
+    dev = torch.device("cuda")
+    lab = torch.empty(64, dtype=torch.uint8, device=dev)
+    spk.classify_boxes(ctx, g, torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev), lab, None, None,
+                       "truncate", 31)
+    spk.classify_boxes(ctx, g, torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev), lab, None, None,
+                       "fixed", 0)
+    st = ctx.sync()
+    assert st["nonfinite_inputs"] == 6
+    assert ctx.sync()["nonfinite_inputs"] == 0
 
 
 def test_degenerate_point_boxes(ctx):

@@ -114,11 +114,23 @@ def test_subdivide_capacity_reports_required(ctx):
     cells = torch.arange(64, dtype=torch.int64, device=dev)   # all level-2 cells
     counts = torch.zeros(4, dtype=torch.int64, device=dev)
     small = torch.full((8,), -1, dtype=torch.int64, device=dev)
+    ctx.sync()
     spk.subdivide_frontier(ctx, g, 2, cells, small, None, counts, 6, "truncate", 31)
+    with pytest.raises(spk.SpkError) as e:
+        ctx.sync()                               # the overflow surfaces at the sync
+    assert e.value.status == spk.E_NOSPC
     c = counts.cpu().numpy()
     assert c[0] > 8 and c[0] % 8 == 0          # required count reported
     assert c[0] // 8 + c[2] + c[3] == 64
     assert np.all(small.cpu().numpy() >= 0)      # only the capacity was written
+    st = ctx.sync()                              # the failed sync cleared the word
+    assert not st["nospc"]
+    spk.subdivide_frontier(ctx, g, 2, cells, small, None, counts, 6, "truncate", 31)
+    st = ctx.sync(allow_nospc=True)
+    assert st["nospc"] and st["need_children"] == c[0] and st["need_leaves"] == 0
+    big = torch.empty(int(c[0]), dtype=torch.int64, device=dev)
+    spk.subdivide_frontier(ctx, g, 2, cells, big, None, counts, 6, "truncate", 31)
+    assert not ctx.sync()["nospc"]
 
 
 def _gpu_rays(ctx, net, o, d, **kw):
