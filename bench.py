@@ -62,38 +62,51 @@ def measured_traffic():
 
 def rays_extra(ctx, g, dev, side=512, seed=600):
     """Procedure 2 on one 512x512 view of the 8x256 blob (eye on the sphere of
-    radius 3.5, 60-degree field of view): rays/s, iterations per ray, and the
-    algorithmic rate of the affine-fixed passes.  One iteration on width-256
-    hidden layers is 3 MFMA columns (segment generator, two passenger points)
-    plus the FP64 center and |W| xinf products, 4 products of 2*256*256 FLOP
-    per hidden layer."""
+    radius 3.5, 60-degree field of view), with rounding-bounded segment bounds
+    (the default) and with the paper's arithmetic: rays/s, iterations per ray,
+    and the algorithmic rate of the affine-fixed passes.  One iteration on
+    width-256 hidden layers is 3 MFMA columns (segment generator, two passenger
+    points) plus the FP64 center and |W| xinf products, 4 products of
+    2*256*256 FLOP per hidden layer."""
     import torch
     import workloads as wl
     from paper_2202_02444_amd import spk
     o, d = wl.camera_rays(side, side, seed)
     to = torch.from_numpy(o).to(dev)
     td = torch.from_numpy(d).to(dev)
-    th = torch.empty(o.shape[0], device=dev)
-    it = torch.empty(o.shape[0], dtype=torch.int32, device=dev)
-    spk.cast_rays(ctx, g, to, td, th, it)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    spk.cast_rays(ctx, g, to, td, th, it)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    its = it.cpu().numpy().astype(np.int64)
     n_hidden = 7
     flop_per_iter = 4 * 2 * 256 * 256 * n_hidden
     edges = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
-    top = max(edges[-1], int(its.max()) if its.size else 0) + 1
-    hist = np.histogram(its, bins=edges + [top])[0]
-    return {"rays": int(o.shape[0]), "rays_per_s": o.shape[0] / dt, "hits": int(torch.isfinite(th).sum().item()),
+
+    def run(rigorous):
+        th = torch.empty(o.shape[0], device=dev)
+        it = torch.empty(o.shape[0], dtype=torch.int32, device=dev)
+        spk.cast_rays(ctx, g, to, td, th, it, rigorous=rigorous)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        spk.cast_rays(ctx, g, to, td, th, it, rigorous=rigorous)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        its = it.cpu().numpy().astype(np.int64)
+        top = max(edges[-1], int(its.max()) if its.size else 0) + 1
+        hist = np.histogram(its, bins=edges + [top])[0]
+        return th.cpu().numpy(), {
+            "rays_per_s": o.shape[0] / dt, "hits": int(torch.isfinite(th).sum().item()),
             "iters_mean": float(its.mean()), "iters_p50": float(np.percentile(its, 50)),
             "iters_p99": float(np.percentile(its, 99)), "iters_max": int(its.max()),
             "iters_hist_log2_edges": edges, "iters_hist": [int(x) for x in hist],
             "iterations_per_s": float(its.sum() / dt), "flop_per_iteration": flop_per_iter,
             "tflops": float(its.sum() * flop_per_iter / dt / 1e12),
             "frac_fp32_mfma": float(its.sum() * flop_per_iter / dt / PEAK_FP32_MFMA)}
+
+    t_rig, rig = run(True)
+    t_pap, pap = run(False)
+    both = np.isfinite(t_rig) & np.isfinite(t_pap)
+    out = {"rays": int(o.shape[0]), "rigorous": rig, "paper": pap,
+           "hit_agreement": float(np.mean(np.isfinite(t_rig) == np.isfinite(t_pap))),
+           "max_abs_dt_common_hits": float(np.abs(t_rig[both] - t_pap[both]).max()) if both.any() else 0.0}
+    out["rays_per_s"] = rig["rays_per_s"]
+    return out
 
 
 def closest_point_extra(ctx, dev, n=4096, max_level=10):

@@ -268,6 +268,10 @@ typedef struct {
   float safety;         /* accepted step fraction, e.g. 0.98                        */
   int32_t max_iters;    /* per-ray iteration cap (> 0)                              */
   int32_t clip_to_domain; /* 1: march each ray over its chord of [-1,1]^3 only     */
+  uint32_t flags;       /* 0: every segment bound carries its rounding bound, so a
+                           step is accepted only when the exact network has no
+                           root on the segment; SPK_FLAG_NO_ROUNDING_BOUND: the
+                           paper's arithmetic with the tolerance margin          */
 } spk_ray_params;
 
 /*

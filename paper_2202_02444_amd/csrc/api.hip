@@ -608,6 +608,7 @@ spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params*
       !isfinite(p.delta) || !isfinite(p.sigma0) || !isfinite(p.eta_plus))
     return SPK_E_INVAL;
   if (!p.clip_to_domain && !(p.t_max > 0.0f && isfinite(p.t_max))) return SPK_E_INVAL;
+  if (p.flags & ~(uint32_t)SPK_FLAG_NO_ROUNDING_BOUND) return SPK_E_INVAL;
   if (n == 0) return SPK_OK;
   if (origin == nullptr || dir == nullptr || t_hit == nullptr) return SPK_E_INVAL;
   void* counter = nullptr;

@@ -12,6 +12,11 @@
 // global atomic counter; a wavefront exits when the counter is exhausted and
 // all its slots are empty, so every wave terminates (at most max_iters
 // iterations per ray).
+//
+// By default the segment bounds carry the rounding bound of every layer (the
+// same folding as the box bounds), so a step is accepted only when the exact
+// network has no root on the segment; SPK_FLAG_NO_ROUNDING_BOUND selects the
+// paper's arithmetic with the tolerance margin.
 #include "affine_stack.h"
 
 namespace spk {
@@ -59,6 +64,7 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
   const int segbase = bo * SEG;
   const int L = net.L;
   const spk_ray_params P = job.p;
+  const bool rig = (P.flags & SPK_FLAG_NO_ROUNDING_BOUND) == 0;
 
   long long rid = -1;   // >= 0 ray index, -1 empty, -2 no rays left
   float t = 0.0f, sigma = 0.0f, f0 = 0.0f, tmax = 0.0f, base = 0.0f;
@@ -153,12 +159,12 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
     layer0_affine<S, NPASS>(net, ch, cc, ax, ein, pts, xc, y, yinf, e);
     for (int a = 0; a < L - 1; ++a) {
       activate<S, ACT, SPK_AFFINE_FIXED, NPASS>(xc, y, yinf, e, u, 1, 0, net.cK, net.cD, net.omega0, lane,
-                                                  nullptr);
+                                                  nullptr, nullptr, rig);
       if (a == L - 2) break;
-      hidden_layer<S, NPASS>(net, sm, a, xc, y, yinf, e, u, lane, false);
+      hidden_layer<S, NPASS>(net, sm, a, xc, y, yinf, e, u, lane, rig);
     }
     float pass[NPASS];
-    const OutVals o = output_layer<S, NPASS>(net, xc, y, yinf, u, lane, pass);
+    const OutVals o = output_layer<S, NPASS>(net, xc, y, yinf, u, lane, pass, rig);
 
     // ---- Procedure 2 update, identical on every lane of the segment
     if (active) {
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(64, 1) void ray_kernel(NetDev net, RayJob job) {
         rid = -1;
       } else {
         float lo, hi;
-        enclose(o, false, lo, hi);
+        enclose(o, rig, lo, hi);
         const bool safe = lo > 0.0f || hi < 0.0f;
         const float step = safe ? P.safety * sigma : 0.0f;
         sigma = safe ? sigma * P.eta_plus : sigma * P.eta_minus;
@@ -222,9 +228,15 @@ __device__ __forceinline__ long long uni(long long v) {
 }
 
 // Activation (affine-fixed) of every ray's rows; passengers get f exactly.
+// With rig the rounding errors are folded into yinf as in activate(): the
+// errors of the producing layer are already in yinf (added where they arise,
+// so no separate register array is live), the linearisation is taken on the
+// whole range, the rounding of the update follows, then the a-priori rounding
+// of the next layer's products (cK |y| + cD |x0|).
 template <int ACT>
 __device__ __forceinline__ void activate_packed(double (&xc)[RPW][4], f4 (&y)[16], float (&yinf)[RPW][4],
-                                                float omega0) {
+                                                const NetDev& net, bool rig) {
+  const float omega0 = net.omega0;
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const int G = 1 + 3 * r;
@@ -234,16 +246,37 @@ __device__ __forceinline__ void activate_packed(double (&xc)[RPW][4], f4 (&y)[16
       y[G + 2][i] = act_point<ACT>(y[G + 2][i], omega0);
       if (ACT == SPK_ACT_SIN) {
         y[G][i] *= omega0;
-        yinf[r][i] *= omega0;
         xc[r][i] *= (double)omega0;
+        if (rig) {
+          const double ys = (double)yinf[r][i] * (double)omega0;
+          yinf[r][i] = round_up_f((ys + (double)kU * ((double)fabsf(y[G][i]) + ys)) * (1.0 + 4.0 * kU64) +
+                                  2.0 * kU64 * fabs(xc[r][i]) + (double)kEta);
+        } else {
+          yinf[r][i] *= omega0;
+        }
       }
       const double x0 = xc[r][i];
-      const double rd = (double)fabsf(y[G][i]) + (double)yinf[r][i];
+      const float rY = fabsf(y[G][i]);
+      double rd = (double)rY + (double)yinf[r][i];
+      if (rig) rd = rd * (1.0 + 4.0 * kU64) + (double)kEta;
       const ActOut p = act_params<ACT>(x0 - rd, x0 + rd, x0);
       const float alf = (float)p.al;
       y[G][i] *= alf;
-      xc[r][i] = fma(p.al, x0, p.be);
-      yinf[r][i] = fabsf(alf) * yinf[r][i] + fmaxf((float)p.ga, 0.0f);
+      const double z0 = fma(p.al, x0, p.be);
+      xc[r][i] = z0;
+      const float zi = fabsf(alf) * yinf[r][i];
+      const float gam = fmaxf((float)p.ga, 0.0f);
+      if (rig) {
+        const double ep = 2.0 * (double)kU * ((double)fabsf(alf) * (double)rY + (double)zi) + 2.0 * kU64 * fabs(z0) +
+                          (double)kU * (double)gam + (double)p.dg + (double)kEta;
+        const double zf = ((double)zi + ep + (double)gam) * (1.0 + 4.0 * kU64);
+        const double rnext = (double)fabsf(alf) * (double)round_up_f(rd) + (double)gam;
+        yinf[r][i] = round_up_f((double)round_up_f(zf) +
+                                ((double)net.cK * rnext + (double)net.cD * fabs(z0)) * (1.0 + 1.52587890625e-05) +
+                                (double)kEta);
+      } else {
+        yinf[r][i] = zi + gam;
+      }
     }
   }
 }
@@ -329,7 +362,7 @@ __device__ __forceinline__ void packed_pass(PackedRayLds<S>& sm, const f4* Wl, c
 // One H -> H layer for the packed rays.
 template <class S>
 __device__ __forceinline__ void hidden_packed(const NetDev& net, PackedRayLds<S>& sm, int a, double (&xc)[RPW][4],
-                                              f4 (&y)[16], float (&yinf)[RPW][4], int lane) {
+                                              f4 (&y)[16], float (&yinf)[RPW][4], int lane, bool rig) {
   constexpr int H = S::H;
 #pragma unroll
   for (int C = 0; C < 16; ++C) *(f4*)&sm.base.tile[taddr<S>(0, C, lane)] = y[C];
@@ -347,13 +380,19 @@ __device__ __forceinline__ void hidden_packed(const NetDev& net, PackedRayLds<S>
 #pragma unroll
   for (int C = 1; C < 16; ++C) y[C] = *(const f4*)&sm.base.tile[taddr<S>(0, C, lane)];
   const f4 bh = *(const f4*)&net.bh[(size_t)a * H + 4 * lane];
+  const f4 eb = *(const f4*)&net.ebh[(size_t)a * H + 4 * lane];
+  const double grow = 1.0 + 2.0 * (double)net.cK;
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const int G = 1 + 3 * r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       xc[r][i] = pd[r][i] + (double)bh[i];
-      yinf[r][i] = px[r][i];
+      // rigorous: |W| yinf summed in FP32 (rounded up by its a-priori bound),
+      // the bias terms and the bias addition of the FP64 center
+      yinf[r][i] = rig ? round_up_f(((double)px[r][i] * grow + (double)eb[i] + 2.0 * kU64 * fabs(xc[r][i])) *
+                                    (1.0 + 2.0 * kU64))
+                       : px[r][i];
       y[G + 1][i] += bh[i];
       y[G + 2][i] += bh[i];
     }
@@ -361,13 +400,15 @@ __device__ __forceinline__ void hidden_packed(const NetDev& net, PackedRayLds<S>
   __syncthreads();
 }
 
-template <class S, int ACT>
+template <class S, int ACT, bool RIG>
 __global__ __launch_bounds__(64, 1) void ray_kernel_packed(NetDev net, RayJob job) {
   static_assert(S::H == 256 && S::NT == 1, "packed rays: width 256, one 16-slot tile");
   __shared__ __attribute__((aligned(16))) PackedRayLds<S> sm;
   const int lane = threadIdx.x;
   const int L = net.L;
   const spk_ray_params P = job.p;
+  // a template flag: both variants stay free of scratch spills
+  constexpr bool rig = RIG;
 
   long long rid[RPW];
   float t[RPW], sigma[RPW], f0[RPW], tmax[RPW], base[RPW], sp[RPW][3], dv[RPW][3];
@@ -459,11 +500,15 @@ __global__ __launch_bounds__(64, 1) void ray_kernel_packed(NetDev net, RayJob jo
           const int G = 1 + 3 * r;
           const bool act = rid[r] >= 0;
           double cc[3];
-          float ax[3], p0[3], p1[3];
+          float ax[3], p0[3], p1[3], ein[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             cc[a] = act ? (double)sp[r][a] + ((double)t[r] + 0.5 * (double)sigma[r]) * (double)dv[r][a] : 0.0;
-            ax[a] = act ? (float)(0.5 * (double)sigma[r] * (double)dv[r][a]) : 0.0f;
+            const double v = act ? 0.5 * (double)sigma[r] * (double)dv[r][a] : 0.0;
+            ax[a] = (float)v;
+            // the segment's center and half-axis as computed against the exact
+            // segment of the ray (FP64 center, FP32 axis)
+            ein[a] = 2.0f * kU * fabsf((float)v) + (float)(4.0 * kU64) * (float)fabs(cc[a]) + kEta;
             p0[a] = act ? sp[r][a] + (t[r] + P.delta) * dv[r][a] : 0.0f;
             p1[a] = act ? sp[r][a] : 0.0f;
           }
@@ -471,14 +516,20 @@ __global__ __launch_bounds__(64, 1) void ray_kernel_packed(NetDev net, RayJob jo
           y[G][i] = fmaf(w.z, ax[2], fmaf(w.y, ax[1], w.x * ax[0]));
           y[G + 1][i] = fmaf(w.z, p0[2], fmaf(w.y, p0[1], fmaf(w.x, p0[0], bb)));
           y[G + 2][i] = fmaf(w.z, p1[2], fmaf(w.y, p1[1], fmaf(w.x, p1[0], bb)));
-          yinf[r][i] = 0.0f;
+          // rigorous: FP32 three-term generator product, FP64 center, input error
+          const float gmag = fabsf(w.x) * fabsf(ax[0]) + fabsf(w.y) * fabsf(ax[1]) + fabsf(w.z) * fabsf(ax[2]);
+          const float cmag = (float)(fabs((double)w.x * cc[0]) + fabs((double)w.y * cc[1]) +
+                                     fabs((double)w.z * cc[2])) + fabsf(bb);
+          yinf[r][i] = rig ? (net.c3 * gmag + (float)(8.0 * kU64) * cmag + fabsf(w.x) * ein[0] +
+                              fabsf(w.y) * ein[1] + fabsf(w.z) * ein[2]) * kGrow + kEta
+                           : 0.0f;
         }
       }
     }
     for (int a = 0; a < L - 1; ++a) {
-      activate_packed<ACT>(xc, y, yinf, net.omega0);
+      activate_packed<ACT>(xc, y, yinf, net, rig);
       if (a == L - 2) break;
-      hidden_packed<S>(net, sm, a, xc, y, yinf, lane);
+      hidden_packed<S>(net, sm, a, xc, y, yinf, lane, rig);
     }
     // ---- output layer per ray and the Procedure 2 update (uniform)
     const f4 wv = *(const f4*)&net.wL[4 * lane];
@@ -503,8 +554,17 @@ __global__ __launch_bounds__(64, 1) void ray_kernel_packed(NetDev net, RayJob jo
       if (rid[r] < 0) continue;
       OutVals o;
       o.y0 = p0 + (double)net.bL;
-      o.r = (float)((double)fabsf(pg) + (double)pinf);
-      o.err = 0.0f;
+      if (rig) {
+        // the products' rounding is already in yinf (folded by the last
+        // activation); add the rounding of |w| yinf, the output bias and the
+        // center
+        o.r = round_up_f(((double)fabsf(pg) + (double)pinf) * (1.0 + 4.0 * kU64));
+        o.err = round_up_f((2.0 * (double)net.cK * (double)pinf + (double)net.eL + 4.0 * kU64 * fabs(o.y0)) *
+                               (1.0 + 4.0 * kU64) + (double)kEta);
+      } else {
+        o.r = (float)((double)fabsf(pg) + (double)pinf);
+        o.err = 0.0f;
+      }
       if (first[r]) {
         f0[r] = q1;
         first[r] = 0;
@@ -518,7 +578,7 @@ __global__ __launch_bounds__(64, 1) void ray_kernel_packed(NetDev net, RayJob jo
         rid[r] = -1;
       } else {
         float lo, hi;
-        enclose(o, false, lo, hi);
+        enclose(o, rig, lo, hi);
         const bool safe = lo > 0.0f || hi < 0.0f;
         const float step = safe ? P.safety * sigma[r] : 0.0f;
         sigma[r] = safe ? sigma[r] * P.eta_plus : sigma[r] * P.eta_minus;
@@ -543,18 +603,31 @@ static hipError_t launch_rays_h(const NetDev& net, const RayJob& job, hipStream_
     int64_t blocks = (int64_t)num_cus * 4;
     if (blocks > nw) blocks = nw;
     if (blocks < 1) blocks = 1;
+    const bool rig = (job.p.flags & SPK_FLAG_NO_ROUNDING_BOUND) == 0;
     switch (net.act) {
       case SPK_ACT_RELU:
-        hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_RELU>), dim3((unsigned)blocks), dim3(64), 0, stream, net,
-                           job);
+        if (rig)
+          hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_RELU, true>), dim3((unsigned)blocks), dim3(64), 0, stream,
+                             net, job);
+        else
+          hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_RELU, false>), dim3((unsigned)blocks), dim3(64), 0, stream,
+                             net, job);
         break;
       case SPK_ACT_ELU:
-        hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_ELU>), dim3((unsigned)blocks), dim3(64), 0, stream, net,
-                           job);
+        if (rig)
+          hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_ELU, true>), dim3((unsigned)blocks), dim3(64), 0, stream,
+                             net, job);
+        else
+          hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_ELU, false>), dim3((unsigned)blocks), dim3(64), 0, stream,
+                             net, job);
         break;
       default:
-        hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_SIN>), dim3((unsigned)blocks), dim3(64), 0, stream, net,
-                           job);
+        if (rig)
+          hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_SIN, true>), dim3((unsigned)blocks), dim3(64), 0, stream,
+                             net, job);
+        else
+          hipLaunchKernelGGL((ray_kernel_packed<S, SPK_ACT_SIN, false>), dim3((unsigned)blocks), dim3(64), 0, stream,
+                             net, job);
         break;
     }
     return hipGetLastError();

@@ -74,7 +74,7 @@ class TreeParams(ctypes.Structure):
 class RayParams(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_float), ("t_max", ctypes.c_float), ("sigma0", ctypes.c_float),
                 ("eta_minus", ctypes.c_float), ("eta_plus", ctypes.c_float), ("safety", ctypes.c_float),
-                ("max_iters", ctypes.c_int32), ("clip_to_domain", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("clip_to_domain", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 Request._fields_ = [("type", ctypes.c_int32), ("net", ctypes.c_int32), ("n", ctypes.c_int64),
@@ -302,10 +302,13 @@ def subdivide_frontier(ctx, net, level, cells, children, leaves, counts, max_lev
 
 
 def ray_params(delta=1e-3, t_max=10.0, sigma0=None, eta_minus=0.5, eta_plus=1.5, safety=0.98, max_iters=100000,
-               clip_to_domain=True):
+               clip_to_domain=True, rigorous=True):
+    """spk_ray_params; rigorous=False selects the paper's arithmetic
+    (SPK_FLAG_NO_ROUNDING_BOUND) for the segment bounds."""
     if sigma0 is None:
         sigma0 = t_max / 10.0
-    return RayParams(delta, t_max, sigma0, eta_minus, eta_plus, safety, int(max_iters), 1 if clip_to_domain else 0)
+    return RayParams(delta, t_max, sigma0, eta_minus, eta_plus, safety, int(max_iters), 1 if clip_to_domain else 0,
+                     0 if rigorous else FLAG_NO_ROUNDING_BOUND)
 
 
 def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):

@@ -128,3 +128,41 @@ def rigorous_vs_oracle(out, lo_o, hi_o, S):
     viol = np.maximum(out["lo"] - lo_o, hi_o - out["hi"]) / S
     w_o = np.maximum(hi_o - lo_o, 1e-300)
     return viol, (out["hi"] - out["lo"]) / w_o
+
+
+def ray_contract_violations(net, o, d, th, rays, delta, tau, h_frac=0.5, min_run=4):
+    """Check GPU ray results against the delta contract of Section 4.1 in
+    FP64: a reported hit t has f(p + (t + delta) r) of the other sign than f at
+    the ray's start, and no region of the other sign at least ~delta long
+    (min_run consecutive samples at spacing h_frac * delta) lies on the ray
+    before the hit (for a miss: anywhere on its chord of [-1,1]^3).  Values
+    with |f| <= tau count as either sign.  Returns a list of (ray, reason)."""
+    o = np.asarray(o, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    t_in, t_out, inside = oq.clip_to_box(o, d)
+    h = h_frac * delta
+    bad = []
+    for i in rays:
+        if not inside[i]:
+            if np.isfinite(th[i]):
+                bad.append((int(i), "hit outside the domain"))
+            continue
+        start = o[i] + t_in[i] * d[i]
+        f0 = omlp.forward_torch(net, start[None])[0]
+        end = (t_out[i] - t_in[i]) if not np.isfinite(th[i]) else min(t_out[i] - t_in[i], th[i] - t_in[i])
+        if np.isfinite(th[i]):
+            fc = omlp.forward_torch(net, (start + (th[i] - t_in[i] + delta) * d[i])[None])[0]
+            if not ((fc > 0) != (f0 > 0) or abs(fc) <= tau or abs(f0) <= tau):
+                bad.append((int(i), "no sign change within delta of the hit"))
+        if abs(f0) <= tau or end <= 0.0:
+            continue
+        s = np.arange(0.0, end, h)
+        f = omlp.forward_torch(net, start[None, :] + s[:, None] * d[i][None, :])
+        opp = ((f > 0) != (f0 > 0)) & (np.abs(f) > tau)
+        run = 0
+        for v in opp:
+            run = run + 1 if v else 0
+            if run >= min_run:
+                bad.append((int(i), "skipped a region of the other sign at least delta long"))
+                break
+    return bad

@@ -124,6 +124,10 @@ def test_tree_and_ray_validation():
     assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp_bad), 4, FAKE, FAKE, FAKE, None) == spk.E_INVAL
     rp_bad2 = spk.ray_params(eta_minus=1.5)
     assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp_bad2), 4, FAKE, FAKE, FAKE, None) == spk.E_INVAL
+    rp_bad3 = spk.ray_params()
+    rp_bad3.flags = 8                          # unknown flag bit
+    assert L.spk_cast_rays(FAKE, FAKE, ctypes.byref(rp_bad3), 4, FAKE, FAKE, FAKE, None) == spk.E_INVAL
+    assert spk.ray_params(rigorous=False).flags == spk.FLAG_NO_ROUNDING_BOUND and spk.ray_params().flags == 0
 
 
 def test_closest_point_validation():

@@ -9,7 +9,7 @@ import workloads as wl
 from oracle import mlp as omlp
 from oracle import queries as oq
 
-from parity import TOL, label_ambiguous, s_net
+from parity import TOL, label_ambiguous, ray_contract_violations, s_net
 
 pytestmark = pytest.mark.gpu
 
@@ -187,10 +187,10 @@ def test_rays_octahedron_closed_form(ctx):
     assert n_hit > 200
 
 
-@pytest.mark.parametrize("netname", ["tiny", "elu64", "blob", "elu256", "sin256"])
-def test_rays_vs_oracle(ctx, netname):
-    """Width 256 runs the packed kernel (several rays per wavefront); the
-    13 x 13 camera leaves a ragged last group of rays."""
+_RAY_ORACLE = {}
+
+
+def _ray_case(netname):
     if netname == "tiny":
         net, side = wl.tiny_net(0), 32
     elif netname == "elu64":
@@ -202,20 +202,43 @@ def test_rays_vs_oracle(ctx, netname):
     else:
         net, side = wl.scale_net(1), 16
     o, d = wl.camera_rays(side, side, 7)
+    if netname not in _RAY_ORACLE:
+        _RAY_ORACLE[netname] = oq.cast_rays(net, o.astype(np.float64), d.astype(np.float64), delta=1e-3)
+    return net, o, d, _RAY_ORACLE[netname]
+
+
+@pytest.mark.parametrize("rigorous", [True, False])
+@pytest.mark.parametrize("netname", ["tiny", "elu64", "blob", "elu256", "sin256"])
+def test_rays_vs_oracle(ctx, netname, rigorous):
+    """Width 256 runs the packed kernel (several rays per wavefront); the
+    13 x 13 camera leaves a ragged last group of rays.  Every ray where the
+    GPU and the oracle disagree (hit vs miss, or hits more than 2 delta apart),
+    and a sample of the others, must satisfy the delta contract (Section 4.1)
+    in FP64; in the rounding-bounded mode no ray may skip a region of the other
+    sign at least delta long."""
+    net, o, d, (to, io) = _ray_case(netname)
     delta = 1e-3
-    th, it = _gpu_rays(ctx, net, o, d, delta=delta)
-    to, io = oq.cast_rays(net, o.astype(np.float64), d.astype(np.float64), delta=delta)
+    th, it = _gpu_rays(ctx, net, o, d, delta=delta, rigorous=rigorous)
     both = np.isfinite(th) & np.isfinite(to)
     agree = np.isfinite(th) == np.isfinite(to)
     assert agree.mean() >= 0.98, agree.mean()
-    assert np.all(np.abs(th[both] - to[both]) <= 2 * delta + 1e-4)
+    near = np.abs(np.where(both, th - to, 0.0)) <= 2 * delta + 1e-4
+    assert near.mean() >= 0.98, near.mean()
+    tau = TOL * s_net(net)
+    differ = np.flatnonzero(~agree | ~near)
+    sample = np.random.default_rng(3).choice(o.shape[0], size=min(24, o.shape[0]), replace=False)
+    bad = ray_contract_violations(net, o, d, th, np.union1d(differ, sample), delta, tau)
+    if rigorous:
+        assert not bad, bad[:5]
+    else:
+        # the paper's arithmetic with the tolerance margin is not a proof: a
+        # rare unsafe step may skip a region, but every hit stays valid
+        assert all(b[1].startswith("skipped") for b in bad), bad[:5]
+        assert len(bad) <= 0.01 * o.shape[0], bad[:5]
     # every reported hit is a sign change of f within delta
     hits = np.flatnonzero(np.isfinite(th))
-    for i in hits[:200]:
-        p0 = o[i].astype(np.float64) + th[i] * d[i].astype(np.float64)
-        start = o[i].astype(np.float64) + oq.clip_to_box(o[i:i + 1], d[i:i + 1])[0][0] * d[i].astype(np.float64)
-        f = omlp.forward(net, np.stack([start, p0 + delta * d[i].astype(np.float64)]))
-        assert (f[0] > 0) != (f[1] > 0) or abs(f[1]) < 1e-4 or abs(f[0]) < 1e-4
+    bad_hits = [b for b in ray_contract_violations(net, o, d, th, hits[:200], delta, tau, min_run=10 ** 9)]
+    assert not bad_hits, bad_hits[:5]
 
 
 def test_rays_edge_cases(ctx):

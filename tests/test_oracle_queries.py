@@ -200,3 +200,26 @@ def test_valid_topk_detects_a_wrong_kept_set():
     rec2 = []
     omlp.bound_boxes(net, lo, hi, "truncate", 8, keep_sets=sets, record=rec2)
     assert valid_topk(rec2) >= 1
+
+
+def test_ray_contract_checker_flags_planted_mistakes():
+    """The delta-contract checker used by the GPU ray tests, pinned on the
+    exact octahedron |x|_1 = R: the oracle's own results pass; a miss on a ray
+    through the solid, a hit moved a quarter of the chord early and a hit
+    moved past the surface are each flagged."""
+    from parity import ray_contract_violations
+    net = wl.octahedron_mlp(0.6)
+    o, d = wl.camera_rays(6, 6, 5, fov_deg=22.0)
+    delta = 1e-3
+    th, _ = q.cast_rays(net, o.astype(np.float64), d.astype(np.float64), delta=delta)
+    rays = np.arange(o.shape[0])
+    assert ray_contract_violations(net, o, d, th, rays, delta, 1e-9) == []
+    hit = np.flatnonzero(np.isfinite(th))
+    assert hit.size >= 4
+    t_in, t_out, _ = q.clip_to_box(o, d)
+    bad = th.copy()
+    bad[hit[0]] = np.inf                                           # missed the solid
+    bad[hit[1]] = t_in[hit[1]] + 0.25 * (th[hit[1]] - t_in[hit[1]])  # no surface there
+    bad[hit[2]] = th[hit[2]] + 0.05                                 # inside, past the surface
+    got = {i for i, _ in ray_contract_violations(net, o, d, bad, rays, delta, 1e-9)}
+    assert got == {int(hit[0]), int(hit[1]), int(hit[2])}
