@@ -380,9 +380,15 @@ spk_status spk_batch_destroy(spk_batch* batch);
  *                     out1 = iters (int32 [n], nullable); ray.
  *   SPK_REQ_CLOSEST   a = query [n][3]; out0 = point [n][3], out1 = dist,
  *                     out2 = bound (float [n], nullable); opts, tree.
- *   bytes             the request's device footprint as the caller counts it
- *                     (inputs + outputs + an estimate of library workspace);
- *                     used only for admission.
+ *   bytes             the request's device footprint: its inputs and outputs
+ *                     plus the library workspace it may use.  Admission keeps
+ *                     the bytes of the requests in flight within the budget,
+ *                     and the library keeps a request's workspace within
+ *                     bytes minus the sizes of its inputs and outputs (closest
+ *                     point shrinks its query chunks to fit; SPK_E_NOMEM when
+ *                     one query's frontier does not fit).  Beyond that the
+ *                     workers hold only their contexts' few hundred bytes of
+ *                     scratch and status.
  * spk_server_poll returns up to max completions (wait != 0: block until one is
  * available or nothing is queued or running).  spk_server_destroy waits for
  * every queued and running request, then stops the workers.
@@ -410,6 +416,7 @@ typedef struct {
   int32_t type;
   int64_t n;
   double submit_s, start_s, done_s;   /* steady-clock seconds                  */
+  uint64_t workspace_bytes;  /* largest library workspace the request held      */
 } spk_completion;
 
 typedef struct spk_server spk_server;

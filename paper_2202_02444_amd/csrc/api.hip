@@ -395,6 +395,7 @@ spk_status spk_ctx_create(void* stream, size_t workspace_bytes, spk_ctx** out) {
   ctx->scratch = nullptr;
   ctx->scratch_bytes = 0;
   ctx->status = nullptr;
+  ctx->ws_peak = 0;
   if (hipGetDevice(&ctx->device) != hipSuccess ||
       hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
     delete ctx;
@@ -620,36 +621,39 @@ spk_status spk_cast_rays(spk_ctx* ctx, const spk_net* net, const spk_ray_params*
 }
 
 namespace {
-// Device buffers owned by one closest-point call.
+// Device buffers owned by one closest-point call, allocated stream-ordered
+// on the context's stream (hipMallocAsync / hipFreeAsync), so that growing or
+// releasing them neither waits for the device nor stalls other streams.
 struct CallBuffers {
   std::vector<std::pair<void**, size_t>> held;
   size_t total = 0;
   size_t limit = 0;
+  size_t* peak = nullptr;   // largest total of the call (nullable)
   hipStream_t stream = nullptr;
   ~CallBuffers() {
-    // kernels of the call may still use the buffers on an error return
-    (void)hipStreamSynchronize(stream);
+    // ordered after every kernel of the call on the stream
     for (auto& h : held)
-      if (*h.first) (void)hipFree(*h.first);
+      if (*h.first) (void)hipFreeAsync(*h.first, stream);
   }
   // (Re)allocate *p to at least `bytes`; contents are not kept.
   spk_status ensure(void** p, size_t& cap, size_t bytes) {
     if (bytes <= cap) return SPK_OK;
     const size_t want = bytes + bytes / 2;
     if (limit && total - cap + want > limit) return SPK_E_NOMEM;
-    // earlier launches of the call may still read the old buffer
-    if (*p && hipStreamSynchronize(stream) != hipSuccess) return SPK_E_DEVICE;
-    if (*p) (void)hipFree(*p);
+    // earlier launches of the call on the stream still read the old buffer:
+    // the stream-ordered free runs after them
+    if (*p) (void)hipFreeAsync(*p, stream);
     *p = nullptr;
     total -= cap;
     cap = 0;
-    if (hipMalloc(p, want) != hipSuccess) {
+    if (hipMallocAsync(p, want, stream) != hipSuccess) {
       *p = nullptr;
       (void)hipGetLastError();   // clear it, so that later launch checks do not report it
       return SPK_E_NOMEM;
     }
     cap = want;
     total += want;
+    if (peak && total > *peak) *peak = total;
     bool known = false;
     for (auto& h : held) known = known || h.first == p;
     if (!known) held.push_back({p, 0});
@@ -663,9 +667,9 @@ struct CallBuffers {
 struct CpBuffers {
   CallBuffers B;
   void *best = nullptr, *codes = nullptr, *qidx = nullptr, *ncodes = nullptr, *nqidx = nullptr, *labels = nullptr,
-       *fpts = nullptr, *fvals = nullptr, *cnt = nullptr;
+       *fpts = nullptr, *fvals = nullptr, *cnt = nullptr, *dcur = nullptr;
   size_t c_best = 0, c_codes = 0, c_qidx = 0, c_ncodes = 0, c_nqidx = 0, c_labels = 0, c_fpts = 0, c_fvals = 0,
-         c_cnt = 0;
+         c_cnt = 0, c_dcur = 0;
 };
 
 static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
@@ -681,6 +685,7 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
   void*& fpts = CB.fpts;
   void*& fvals = CB.fvals;
   void*& cnt = CB.cnt;
+  void*& dcur = CB.dcur;
   size_t& c_best = CB.c_best;
   size_t& c_codes = CB.c_codes;
   size_t& c_qidx = CB.c_qidx;
@@ -702,6 +707,58 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
   SPK_ENSURE(cnt, c_cnt, 256);
   st = launch_cp_init(n, (uint64_t*)codes, (uint32_t*)qidx, (unsigned*)best, point, ctx->stream, ctx->num_cus);
   if (st != SPK_OK) return st;
+  if (rigorous_opts(opts) && tree->max_level >= 1) {
+    // seeding descent (closest.hip): under sound bounds every cell it uses is
+    // one the level rounds would reach, so the result does not change; the
+    // frontier buffers of the rounds serve as its child buffers
+    SPK_ENSURE(dcur, CB.c_dcur, (size_t)n * 8);
+    SPK_ENSURE(ncodes, c_ncodes, (size_t)n * 8 * 8);
+    SPK_ENSURE(labels, c_labels, (size_t)n * 8);
+    SPK_ENSURE(fpts, c_fpts, (size_t)n * 48 * 12);
+    SPK_ENSURE(fvals, c_fvals, (size_t)n * 48 * 4);
+    st = launch_cp_dive_init(n, (uint64_t*)dcur, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+    for (int level = 1; level <= tree->max_level; ++level) {
+      CpDive D = {};
+      D.n = n;
+      D.level = level;
+      for (int d = 0; d < 3; ++d) {
+        D.dom_lo[d] = tree->dom_lo[d];
+        D.dom_hi[d] = tree->dom_hi[d];
+      }
+      D.q = q;
+      D.cur = (uint64_t*)dcur;
+      D.codes = (uint64_t*)ncodes;
+      D.label = (const uint8_t*)labels;
+      D.fpts = (float*)fpts;
+      D.fvals = (const float*)fvals;
+      D.best = (unsigned*)best;
+      D.point = point;
+      st = launch_cp_dive_children(D, ctx->stream, ctx->num_cus);
+      if (st != SPK_OK) return st;
+      BoundJob job = {};
+      job.n = 8 * n;
+      job.mode = IN_CELL;
+      job.s = 3;
+      job.policy = opts->policy;
+      job.k = opts->k;
+      job.prec = opts->prec;
+      job.rigorous = 1;
+      job.cells = (const uint64_t*)ncodes;
+      job.level = level;
+      for (int d = 0; d < 3; ++d) {
+        job.dom_lo[d] = tree->dom_lo[d];
+        job.dom_hi[d] = tree->dom_hi[d];
+      }
+      job.label = (uint8_t*)labels;
+      st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+      if (st != SPK_OK) return st;
+      st = launch_eval(net, 48 * n, (const float*)fpts, (float*)fvals, ctx->stream, ctx->num_cus);
+      if (st != SPK_OK) return st;
+      st = launch_cp_dive_pick(D, ctx->stream, ctx->num_cus);
+      if (st != SPK_OK) return st;
+    }
+  }
   int64_t m = n;
   for (int level = 0; level <= tree->max_level && m > 0; ++level) {
     const bool at_max = level == tree->max_level;
@@ -790,6 +847,7 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
   CpBuffers CB;
   CB.B.limit = ctx->workspace_limit ? ctx->workspace_limit : ((size_t)16 << 30);
   CB.B.stream = ctx->stream;
+  CB.B.peak = &ctx->ws_peak;
   for (int64_t c0 = 0; c0 < n;) {
     const int64_t cn = (n - c0 < chunk) ? n - c0 : chunk;
     st = closest_chunk(ctx, net, opts, tree, cn, q + 3 * c0, point + 3 * c0, dist ? dist + c0 : nullptr,

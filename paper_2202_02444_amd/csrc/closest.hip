@@ -60,21 +60,37 @@ __global__ __launch_bounds__(256) void cp_init_kernel(int64_t n, uint64_t* codes
   }
 }
 
-// Face centers of every frontier cell: 6 points per cell, the cell center
-// with one coordinate moved to a face.
+// The 6 face centers of a cell (the cell center with one coordinate moved to
+// a face), written as 18 floats.  The level rounds and the seeding descent
+// both use this, so a cell's spanning test is the same in either.
+__device__ __forceinline__ void write_faces(const float (&lo)[3], const float (&hi)[3], float* out) {
+  float c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) c[d] = 0.5f * (lo[d] + hi[d]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) out[(2 * a + sd) * 3 + d] = (d == a) ? (sd ? hi[d] : lo[d]) : c[d];
+}
+
+__device__ __forceinline__ bool spans6(const float* v) {
+  bool neg = false, pos = false;
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    neg = neg || v[p] < 0.0f;
+    pos = pos || v[p] > 0.0f;
+  }
+  return neg && pos;
+}
+
+// Face centers of every frontier cell.
 __global__ __launch_bounds__(256) void cp_faces_kernel(CpLevel L) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.m; i += (int64_t)gridDim.x * blockDim.x) {
     float lo[3], hi[3];
     cp_cell_box(L.codes[i], L.level, L, lo, hi);
-    float c[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) c[d] = 0.5f * (lo[d] + hi[d]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) L.fpts[(6 * i + 2 * a + sd) * 3 + d] = (d == a) ? (sd ? hi[d] : lo[d]) : c[d];
+    write_faces(lo, hi, L.fpts + 18 * i);
   }
 }
 
@@ -87,16 +103,7 @@ __device__ __forceinline__ bool cp_live(const CpLevel& L, int64_t i, float (&q)[
   return L.label[i] == SPK_UNKNOWN && min_dist(q, lo, hi) < bound;
 }
 
-__device__ __forceinline__ bool cp_spans(const CpLevel& L, int64_t i) {
-  bool neg = false, pos = false;
-#pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    const float v = L.fvals[6 * i + p];
-    neg = neg || v < 0.0f;
-    pos = pos || v > 0.0f;
-  }
-  return neg && pos;
-}
+__device__ __forceinline__ bool cp_spans(const CpLevel& L, int64_t i) { return spans6(L.fvals + 6 * i); }
 
 __global__ __launch_bounds__(256) void cp_update_kernel(CpLevel L) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.m; i += (int64_t)gridDim.x * blockDim.x) {
@@ -199,6 +206,84 @@ __global__ __launch_bounds__(256) void cp_finish_kernel(int64_t n, const float* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Seeding descent.  Before the level rounds every query walks down from the
+// root one cell per level: of the current cell's 8 children it enters the
+// nearest (minimum distance) UNKNOWN child that spans the surface, else the
+// nearest UNKNOWN child, and it lowers its bound by the farthest distance to
+// the best spanning UNKNOWN child.  The walk stops when no child is UNKNOWN
+// or the nearest one is not closer than the bound.
+//
+// Every cell that lowers the seed is a spanning UNKNOWN cell whose ancestors
+// are UNKNOWN (the path), tested with the same face centers, evaluation and
+// distance functions as the level rounds.  The rounds reach such a cell
+// unless a bound below its farthest distance prunes an ancestor first, so
+// with or without the seed they end with the same bound: the seed only prunes
+// cells that could not lower it.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kDead = ~0ull;
+
+__global__ __launch_bounds__(256) void cp_dive_init_kernel(int64_t n, uint64_t* cur) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    cur[i] = 0ull;   // the root
+}
+
+__global__ __launch_bounds__(256) void cp_dive_children_kernel(CpDive D) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 8 * D.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = D.cur[i >> 3];
+    // a stopped query still fills its 8 slots (with a valid cell) so that
+    // every label and face value read later is written
+    const uint64_t code = (c == kDead) ? 0ull : ((c << 3) | (uint64_t)(i & 7));
+    D.codes[i] = code;
+    float lo[3], hi[3];
+    cell_box(code, D.level, D.dom_lo, D.dom_hi, lo, hi);
+    write_faces(lo, hi, D.fpts + 18 * i);
+  }
+}
+
+__global__ __launch_bounds__(256) void cp_dive_pick_kernel(CpDive D) {
+  for (int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; qi < D.n; qi += (int64_t)gridDim.x * blockDim.x) {
+    if (D.cur[qi] == kDead) continue;
+    float q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) q[d] = D.q[3 * qi + d];
+    int pick = -1, best_span = -1;
+    bool pick_spans = false;
+    float pick_min = INFINITY;
+    unsigned bmax = 0xffffffffu;
+    for (int o = 0; o < 8; ++o) {
+      const int64_t i = 8 * qi + o;
+      if (D.label[i] != SPK_UNKNOWN) continue;
+      float lo[3], hi[3];
+      cell_box(D.codes[i], D.level, D.dom_lo, D.dom_hi, lo, hi);
+      const bool sp = spans6(D.fvals + 6 * i);
+      const float md = min_dist(q, lo, hi);
+      if (pick < 0 || (sp && !pick_spans) || (sp == pick_spans && md < pick_min)) {
+        pick = o;
+        pick_spans = sp;
+        pick_min = md;
+      }
+      if (sp) {
+        const unsigned b = __float_as_uint(max_dist(q, lo, hi));
+        if (b < bmax) {
+          bmax = b;
+          best_span = o;
+        }
+      }
+    }
+    if (best_span >= 0 && bmax < D.best[qi]) {
+      D.best[qi] = bmax;
+      float lo[3], hi[3];
+      cell_box(D.codes[8 * qi + best_span], D.level, D.dom_lo, D.dom_hi, lo, hi);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) D.point[3 * qi + d] = 0.5f * (lo[d] + hi[d]);
+    }
+    const bool go = pick >= 0 && pick_min < __uint_as_float(D.best[qi]);
+    D.cur[qi] = go ? D.codes[8 * qi + pick] : kDead;
+  }
+}
+
 static inline unsigned grid_for(int64_t n, int num_cus) {
   int64_t b = (n + 255) / 256;
   if (b > (int64_t)num_cus * 8) b = (int64_t)num_cus * 8;
@@ -224,6 +309,21 @@ spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t str
     hipLaunchKernelGGL(cp_zero_kernel, dim3(1), dim3(64), 0, stream, L.ncount);
     hipLaunchKernelGGL(cp_expand_kernel, dim3(g), dim3(256), 0, stream, L);
   }
+  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+}
+
+spk_status launch_cp_dive_init(int64_t n, uint64_t* cur, hipStream_t stream, int num_cus) {
+  hipLaunchKernelGGL(cp_dive_init_kernel, dim3(grid_for(n, num_cus)), dim3(256), 0, stream, n, cur);
+  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+}
+
+spk_status launch_cp_dive_children(const CpDive& D, hipStream_t stream, int num_cus) {
+  hipLaunchKernelGGL(cp_dive_children_kernel, dim3(grid_for(8 * D.n, num_cus)), dim3(256), 0, stream, D);
+  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+}
+
+spk_status launch_cp_dive_pick(const CpDive& D, hipStream_t stream, int num_cus) {
+  hipLaunchKernelGGL(cp_dive_pick_kernel, dim3(grid_for(D.n, num_cus)), dim3(256), 0, stream, D);
   return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
 }
 

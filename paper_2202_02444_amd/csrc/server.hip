@@ -69,6 +69,19 @@ spk_status run_request(spk_ctx* ctx, const spk_server* s, const spk_request& r) 
   return SPK_E_INVAL;
 }
 
+// Bytes of a request's inputs and outputs (device memory the caller owns).
+size_t io_bytes(const spk_request& r) {
+  const size_t n = (size_t)r.n;
+  switch (r.type) {
+    case SPK_REQ_CLASSIFY:
+      return n * 24 + n + (r.out1 ? n * 4 : 0) + (r.out2 ? n * 4 : 0);
+    case SPK_REQ_RAYS:
+      return n * 24 + n * 4 + (r.out1 ? n * 4 : 0);
+    default:
+      return n * 12 + n * 12 + (r.out1 ? n * 4 : 0) + (r.out2 ? n * 4 : 0);
+  }
+}
+
 void worker_main(spk_server* s, spk_ctx* ctx) {
   for (;;) {
     Pending p;
@@ -89,6 +102,12 @@ void worker_main(spk_server* s, spk_ctx* ctx) {
       ++s->busy;
     }
     const double start = now_s();
+    // a closest-point request's workspace stays within its declared bytes
+    // beyond its inputs and outputs (box and ray requests use none beyond the
+    // context's fixed 4 KiB of scratch)
+    const size_t io = io_bytes(p.req);
+    ctx->workspace_limit = p.req.type != SPK_REQ_CLOSEST ? 0 : (p.req.bytes > io ? p.req.bytes - io : 1);
+    ctx->ws_peak = 0;
     spk_status st = run_request(ctx, s, p.req);
     if (st == SPK_OK) st = spk_ctx_sync(ctx, nullptr);
     const double end = now_s();
@@ -104,6 +123,7 @@ void worker_main(spk_server* s, spk_ctx* ctx) {
       c.submit_s = p.submit_s;
       c.start_s = start;
       c.done_s = end;
+      c.workspace_bytes = ctx->ws_peak;
       s->done.push_back(c);
     }
     s->cv_work.notify_all();

@@ -114,6 +114,23 @@ struct CpLevel {
   int64_t cap;
 };
 
+// Greedy descent that seeds the closest-point bound before the level rounds
+// (closest.hip): one current cell per query, its 8 children per level.
+struct CpDive {
+  int64_t n;                 // queries
+  int level;                 // level of the children
+  float dom_lo[3];
+  float dom_hi[3];
+  const float* q;            // [n][3] queries
+  uint64_t* cur;             // [n] current cell (one level up); all ones: stopped
+  uint64_t* codes;           // [8n] children
+  const uint8_t* label;      // [8n] classification of the children
+  float* fpts;               // [48n][3] face centers of the children
+  const float* fvals;        // [48n] f at the face centers
+  unsigned* best;            // [n] distance bounds (float bits)
+  float* point;              // [n][3] candidates
+};
+
 }  // namespace spk
 
 struct spk_net {
@@ -139,6 +156,8 @@ struct spk_ctx {
   size_t scratch_bytes;
   // device status word (spk_device_status layout), cleared by spk_ctx_sync
   void* status;
+  // largest per-call workspace of the closest-point calls since it was reset
+  size_t ws_peak;
 };
 
 namespace spk {
@@ -175,6 +194,9 @@ spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, c
 spk_status launch_cp_init(int64_t n, uint64_t* codes, uint32_t* qidx, unsigned* best, float* point,
                           hipStream_t stream, int num_cus);
 spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t stream, int num_cus);
+spk_status launch_cp_dive_init(int64_t n, uint64_t* cur, hipStream_t stream, int num_cus);
+spk_status launch_cp_dive_children(const CpDive& D, hipStream_t stream, int num_cus);
+spk_status launch_cp_dive_pick(const CpDive& D, hipStream_t stream, int num_cus);
 spk_status launch_cp_finish(int64_t n, const float* q, const unsigned* best, float* point, float* dist,
                             float* best_out, hipStream_t stream, int num_cus);
 }  // namespace spk

@@ -48,7 +48,7 @@ class Request(ctypes.Structure):
 class Completion(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("type", ctypes.c_int32),
                 ("n", ctypes.c_int64), ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
-                ("done_s", ctypes.c_double)]
+                ("done_s", ctypes.c_double), ("workspace_bytes", ctypes.c_uint64)]
 
 
 class BoundOpts(ctypes.Structure):
@@ -441,7 +441,10 @@ class Server:
             r.tree = TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1),
                                 int(req.get("max_level", 8)), 8)
             tensors = [req["q"], req["point"], req.get("dist"), req.get("bound")]
-        r.bytes = int(req.get("bytes", sum(t.numel() * t.element_size() for t in tensors if t is not None)))
+        io = sum(t.numel() * t.element_size() for t in tensors if t is not None)
+        # default workspace: none for boxes and rays, 64 MiB for closest points
+        ws = req.get("workspace", (64 << 20) if req["type"] == "closest" else 0)
+        r.bytes = int(req.get("bytes", io + ws))
         rid = ctypes.c_uint64()
         _check(lib().spk_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)), "spk_server_submit")
         self._live[rid.value] = tensors
@@ -456,7 +459,7 @@ class Server:
             c = out[i]
             self._live.pop(c.id, None)
             res.append({"id": c.id, "status": c.status, "type": c.type, "n": c.n, "submit_s": c.submit_s,
-                        "start_s": c.start_s, "done_s": c.done_s})
+                        "start_s": c.start_s, "done_s": c.done_s, "workspace_bytes": int(c.workspace_bytes)})
         return res
 
     def pending(self):

@@ -116,9 +116,29 @@ def test_admission_respects_the_memory_budget(env, fit):
     requests run at once although four workers are free."""
     spk, nets, ctx = env
     reqs = _make_requests(6)[:9]
-    B = 1 << 20
+    B = 64 << 20   # closest-point requests keep their workspace within it
     for r in reqs:
         r["bytes"] = B
     ids, done = _run_server(spk, nets, reqs, budget=fit * B, workers=4)
     assert all(c["status"] == spk.OK for c in done)
     assert _max_concurrent(done) <= fit
+
+
+def test_request_workspace_stays_within_declared_bytes(env):
+    """A closest-point request's library workspace stays within its declared
+    bytes beyond its inputs and outputs (the query chunks shrink to fit), and
+    its results are those of the unconstrained call."""
+    spk, nets, ctx = env
+    reqs = [r for r in _make_requests(11) if r["type"] == "closest"]
+    ws = 2 << 20
+    for r in reqs:
+        r["workspace"] = ws
+    alone = [_alone(spk, nets, ctx, r) for r in reqs]
+    ids, done = _run_server(spk, nets, reqs, budget=64 << 20, workers=3)
+    by_id = {c["id"]: c for c in done}
+    for rid, r, a in zip(ids, reqs, alone):
+        c = by_id[rid]
+        assert c["status"] == spk.OK
+        assert 0 < c["workspace_bytes"] <= ws, (c["workspace_bytes"], ws)
+        for k in OUT_KEYS["closest"]:
+            np.testing.assert_array_equal(r[k].cpu().numpy(), a[k])
