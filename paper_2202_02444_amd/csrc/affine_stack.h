@@ -187,17 +187,32 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
       mine[q] = sel ? kold[C] : mine[q];
       minev[q] = sel ? (C <= n_occ) : minev[q];
     }
-    // radix select of the k-th largest key, most significant bit first
+    // radix select of the k-th largest key, most significant bit first.  It
+    // stops as soon as the keys >= T are exactly k (the remaining bits cannot
+    // change the kept set), and does not start when at most k keys are
+    // nonzero (T = 0 keeps them all).  The loop exits when every box of the
+    // wave is done, so the ballots always run on the whole wave.
     uint32_t T = 0u;
+    {
+      int cpos = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cpos += seg_count<SEG>(minev[q] && mine[q] != 0u, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cpos += seg_count<SEG>(knew[i] != 0u, lane);
+      bool done = cpos <= k;
 #pragma unroll 1
-    for (int bit = 30; bit >= 0; --bit) {
-      const uint32_t Tc = T | (1u << bit);
-      int cnt = 0;
+      for (int bit = 30; bit >= 0; --bit) {
+        if (__ballot(!done) == 0ull) break;
+        const uint32_t Tc = T | (1u << bit);
+        int cnt = 0;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) cnt += seg_count<SEG>(minev[q] && mine[q] >= Tc, lane);
+        for (int q = 0; q < Q; ++q) cnt += seg_count<SEG>(minev[q] && mine[q] >= Tc, lane);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) cnt += seg_count<SEG>(knew[i] >= Tc, lane);
-      T = (cnt >= k) ? Tc : T;
+        for (int i = 0; i < 4; ++i) cnt += seg_count<SEG>(knew[i] >= Tc, lane);
+        const bool take = !done && cnt >= k;
+        T = take ? Tc : T;
+        done = done || (take && cnt == k);
+      }
     }
     const uint32_t tau = T;
     int cgt = 0;

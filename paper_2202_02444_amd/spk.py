@@ -283,12 +283,13 @@ def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=Non
 
 
 def subdivide_frontier(ctx, net, level, cells, children, leaves, counts, max_level, policy="truncate", k=31,
-                       dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8, noalloc=False, rigorous=True):
+                       dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8, noalloc=False, rigorous=True,
+                       prec="f32"):
     """One round of Procedure 3 (spk_subdivide_frontier, or with
     noalloc=True spk_subdivide_frontier_noalloc)."""
     import torch
     tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), int(arity))
-    o = opts(policy, k, rigorous)
+    o = opts(policy, k, rigorous, prec)
     n = cells.shape[0]
     capc = children.shape[0] if children is not None else 0
     capl = leaves.shape[0] if leaves is not None else 0
@@ -323,12 +324,12 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
 
 
 def closest_point(ctx, net, q, point, dist=None, bound=None, max_level=8, policy="fixed", k=31,
-                  dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), rigorous=True):
+                  dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), rigorous=True, prec="f32"):
     """spk_closest_point: point [n, 3], dist [n] and bound [n] for queries q [n, 3]."""
     import torch
     n = q.shape[0]
     tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), 8)
-    o = opts(policy, k, rigorous)
+    o = opts(policy, k, rigorous, prec)
     st = lib().spk_closest_point(ctx.handle, net.handle, ctypes.byref(o), ctypes.byref(tp), n,
                                  _ptr(q, torch.float32, (n, 3), "q"), _ptr(point, torch.float32, (n, 3), "point"),
                                  _ptr(dist, torch.float32, (n,), "dist"), _ptr(bound, torch.float32, (n,), "bound"))
@@ -490,7 +491,7 @@ def eval_points(ctx, net, x, f):
 
 
 def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3,
-                 cap=1 << 26, rigorous=True):
+                 cap=1 << 26, rigorous=True, prec="f32"):
     """Fixed-depth octree by repeated spk_subdivide_frontier rounds (the
     breadth-first parallel rounds of Procedure 3).  Returns per-level stats and
     the UNKNOWN leaf cells at max_level (GPU tensor)."""
@@ -508,7 +509,7 @@ def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 
         children = torch.empty(max(capc, 1), dtype=torch.int64, device=dev)
         lv = torch.empty(max(capl, 1), dtype=torch.int64, device=dev)
         subdivide_frontier(ctx, net, level, cells, children[:capc] if capc else None, lv[:capl] if capl else None,
-                           counts, max_level, policy, k, dom_lo, dom_hi, rigorous=rigorous)
+                           counts, max_level, policy, k, dom_lo, dom_hi, rigorous=rigorous, prec=prec)
         ds = ctx.sync(allow_nospc=True)
         c = counts.cpu().tolist()
         levels.append({"level": level, "n": n, "n_children": c[0], "n_leaves": c[1], "n_pos": c[2], "n_neg": c[3]})
