@@ -6,6 +6,8 @@
   extraction, Section 4.7), octree (arity 8) or k-d (arity 2) splits.
 * :func:`cast_rays`     -- Procedure 2 with the Appendix B step safety factor.
 * :func:`closest_point` -- Section 4.10 lazy best-first descent.
+* :func:`cast_frusta`   -- Section 4.3 frustum ray casting (Appendix B split
+  rule and spherical-front box), ending in Procedure 2 per pixel.
 """
 from __future__ import annotations
 
@@ -305,3 +307,156 @@ def closest_point(net, q, max_level=8, policy="fixed", k=31, dom_lo=(-1, -1, -1)
     if point is None:
         return None, math.inf, math.inf
     return point, float(np.linalg.norm(point - q)), best
+
+
+# ---------------------------------------------------------------------------
+# Frustum ray casting (Section 4.3; Appendix B)
+# ---------------------------------------------------------------------------
+
+def pixel_coords(cam, px, py):
+    """Tangent-plane coordinates (x, y) of pixel centers."""
+    x = (2.0 * (np.asarray(px, dtype=np.float64) + 0.5) / cam["width"] - 1.0) * cam["tan_x"]
+    y = (1.0 - 2.0 * (np.asarray(py, dtype=np.float64) + 0.5) / cam["height"]) * cam["tan_y"]
+    return x, y
+
+
+def pixel_dirs(cam, px, py):
+    """Unit directions normalize(forward + x right + y up) of pixel centers."""
+    x, y = pixel_coords(cam, px, py)
+    d = np.asarray(cam["forward"], dtype=np.float64)[None, :] + np.asarray(x)[..., None] * \
+        np.asarray(cam["right"], dtype=np.float64)[None, :] + np.asarray(y)[..., None] * \
+        np.asarray(cam["up"], dtype=np.float64)[None, :]
+    return d / np.linalg.norm(d, axis=-1, keepdims=True)
+
+
+def frustum_box(cam, x0, x1, y0, y1, t, sigma):
+    """Oriented box (center [m, 3], axes [m, 3, 3]) bounding the part of each
+    frustum between distances t and t + sigma along its rays: the points
+    eye + s d with s in [t, t + sigma] and d any ray through the tangent-plane
+    rectangle spanned by the centers of pixels x0..x1-1, y0..y1-1.
+
+    The box is taken in the camera frame (forward, right, up).  A point has
+    coordinates s (1, x, y) / sqrt(1 + x^2 + y^2); each coordinate is
+    monotone in x (or y) with the other fixed, so its extremes lie on the
+    rectangle's edges at the smallest or largest |x|, |y|.  The forward
+    extent reaches (t + sigma) / sqrt(1 + x^2 + y^2) at the point of the
+    rectangle nearest the axis, beyond the front face through the corner
+    rays: the rays sweep a spherical front (Appendix B)."""
+    x0, x1, y0, y1 = (np.asarray(v, dtype=np.int64) for v in (x0, x1, y0, y1))
+    t = np.asarray(t, dtype=np.float64)
+    s1 = t + np.asarray(sigma, dtype=np.float64)
+    xa, _ = pixel_coords(cam, x0, 0)
+    xb, _ = pixel_coords(cam, x1 - 1, 0)
+    _, ya = pixel_coords(cam, 0, y1 - 1)     # y decreases down the image
+    _, yb = pixel_coords(cam, 0, y0)
+    xlo, xhi = np.minimum(xa, xb), np.maximum(xa, xb)
+    ylo, yhi = np.minimum(ya, yb), np.maximum(ya, yb)
+
+    def near0(lo, hi):
+        return np.where((lo <= 0.0) & (hi >= 0.0), 0.0, np.minimum(np.abs(lo), np.abs(hi)))
+
+    mx2, my2 = near0(xlo, xhi) ** 2, near0(ylo, yhi) ** 2
+    Mx2, My2 = np.maximum(xlo ** 2, xhi ** 2), np.maximum(ylo ** 2, yhi ** 2)
+    f_lo = t / np.sqrt(1.0 + Mx2 + My2)
+    f_hi = s1 / np.sqrt(1.0 + mx2 + my2)
+
+    def lateral(lo, hi, o_min2, o_max2):
+        gmax = hi / np.sqrt(1.0 + hi ** 2 + np.where(hi >= 0.0, o_min2, o_max2))
+        gmin = lo / np.sqrt(1.0 + lo ** 2 + np.where(lo <= 0.0, o_min2, o_max2))
+        cmax = np.where(gmax >= 0.0, s1 * gmax, t * gmax)
+        cmin = np.where(gmin <= 0.0, s1 * gmin, t * gmin)
+        return cmin, cmax
+
+    r_lo, r_hi = lateral(xlo, xhi, my2, My2)
+    u_lo, u_hi = lateral(ylo, yhi, mx2, Mx2)
+    frame = np.stack([np.asarray(cam["forward"], dtype=np.float64), np.asarray(cam["right"], dtype=np.float64),
+                      np.asarray(cam["up"], dtype=np.float64)])
+    lo = np.stack([f_lo, r_lo, u_lo], axis=-1)
+    hi = np.stack([f_hi, r_hi, u_hi], axis=-1)
+    mid = 0.5 * (lo + hi)
+    half = 0.5 * (hi - lo)
+    center = np.asarray(cam["eye"], dtype=np.float64)[None, :] + mid @ frame
+    axes = half[..., None] * frame[None, :, :]
+    return center, axes
+
+
+def cast_frusta(net, cam, tiles=(16, 16), delta=1e-3, sigma0=1.0, eta_minus=0.5, eta_plus=1.5, safety=0.98,
+                max_iters=100000, policy="fixed", k=31):
+    """Frustum ray casting of the camera's image (Section 4.3): a tiles[0] x
+    tiles[1] grid of coarse frusta over the pixels marches forward in steps
+    like CastRay, each step bounding f over the oriented box of the frustum
+    between t and t + sigma (:func:`frustum_box`).  A step is accepted
+    (t += safety sigma, sigma grows by eta_plus) when the box misses the domain
+    [-1,1]^3 or f is bounded away from zero on it; otherwise sigma shrinks by
+    eta_minus, and a frustum whose width along an image direction at
+    distance t + sigma exceeds 2 sigma (or whose sigma fell below delta) is
+    split in half along its wider direction (Appendix B).  A frustum of one
+    pixel continues as that pixel's ray from t (CastRay over the ray's chord
+    of the domain).  Frusta start at the distance of the domain's bounding
+    sphere and stop, all their rays missing, past its far side.
+
+    Returns (t_hit [height * width] along each pixel's unit ray, +inf for no
+    hit; steps [height * width]: frustum steps plus ray iterations)."""
+    W, H = cam["width"], cam["height"]
+    eye = np.asarray(cam["eye"], dtype=np.float64)
+    R = math.sqrt(3.0)
+    t0 = max(0.0, float(np.linalg.norm(eye)) - R)
+    t_far = float(np.linalg.norm(eye)) + R
+    t_hit = np.full(W * H, np.inf)
+    steps = np.zeros(W * H, dtype=np.int64)
+    xs = [int(round(i * W / tiles[0])) for i in range(tiles[0] + 1)]
+    ys = [int(round(j * H / tiles[1])) for j in range(tiles[1] + 1)]
+    fr = [[xs[i], xs[i + 1], ys[j], ys[j + 1], t0, float(sigma0)]
+          for j in range(tiles[1]) for i in range(tiles[0]) if xs[i + 1] > xs[i] and ys[j + 1] > ys[j]]
+    hand_pix, hand_t = [], []
+    while fr:
+        F = np.array(fr, dtype=np.float64)
+        x0, x1, y0, y1 = (F[:, i].astype(np.int64) for i in range(4))
+        t, sg = F[:, 4], F[:, 5]
+        c, ax = frustum_box(cam, x0, x1, y0, y1, t, sg)
+        lo_y, hi_y = mlp.bound_general(net, c, ax, policy, k)
+        ext = np.abs(ax).sum(axis=1)
+        miss = np.any((c - ext > 1.0) | (c + ext < -1.0), axis=1)
+        safe = miss | (classify(lo_y, hi_y) != UNKNOWN)
+        xa, _ = pixel_coords(cam, x0, 0)
+        xb, _ = pixel_coords(cam, x1 - 1, 0)
+        _, ya = pixel_coords(cam, 0, y1 - 1)
+        _, yb = pixel_coords(cam, 0, y0)
+        nxt = []
+        for i in range(len(fr)):
+            a0, a1, b0, b1, ti, si = fr[i]
+            steps[(np.arange(b0, b1)[:, None] * W + np.arange(a0, a1)[None, :]).ravel()] += 1
+            if safe[i]:
+                ti += safety * si
+                si *= eta_plus
+                if ti < t_far:
+                    nxt.append([a0, a1, b0, b1, ti, si])
+                continue
+            si *= eta_minus
+            nx, ny = a1 - a0, b1 - b0
+            if nx == 1 and ny == 1:
+                hand_pix.append(b0 * W + a0)
+                hand_t.append(ti)
+                continue
+            wx = (ti + si) * abs(xb[i] - xa[i])
+            wy = (ti + si) * abs(yb[i] - ya[i])
+            if max(wx, wy) > 2.0 * si or si < delta:
+                if ny == 1 or (nx > 1 and wx >= wy):
+                    m = (a0 + a1) // 2
+                    nxt += [[a0, m, b0, b1, ti, si], [m, a1, b0, b1, ti, si]]
+                else:
+                    m = (b0 + b1) // 2
+                    nxt += [[a0, a1, b0, m, ti, si], [a0, a1, m, b1, ti, si]]
+            else:
+                nxt.append([a0, a1, b0, b1, ti, si])
+        fr = nxt
+    if hand_pix:
+        pix = np.array(hand_pix, dtype=np.int64)
+        th = np.array(hand_t)
+        d = pixel_dirs(cam, pix % W, pix // W)
+        rel, it = cast_rays(net, eye[None, :] + th[:, None] * d, d, delta=delta, sigma0=sigma0 * 1.0,
+                            eta_minus=eta_minus, eta_plus=eta_plus, safety=safety, max_iters=max_iters,
+                            clip_to_domain=True, policy="fixed", k=k)
+        t_hit[pix] = th + rel
+        steps[pix] += it
+    return t_hit, steps

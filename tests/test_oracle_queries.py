@@ -223,3 +223,96 @@ def test_ray_contract_checker_flags_planted_mistakes():
     bad[hit[2]] = th[hit[2]] + 0.05                                 # inside, past the surface
     got = {i for i, _ in ray_contract_violations(net, o, d, bad, rays, delta, 1e-9)}
     assert got == {int(hit[0]), int(hit[1]), int(hit[2])}
+
+
+def test_frustum_box_contains_the_swept_region_and_is_tight():
+    """Brute force over sampled rays and distances: every point of a frustum
+    between t and t + sigma lies in the oriented box, and each face of the box
+    is reached by the region (up to the sampling density), including the
+    forward face beyond the corner rays' front."""
+    cam = wl.camera(40, 30, 9, fov_deg=70.0)
+    rng = np.random.default_rng(4)
+    frame = np.stack([cam["forward"], cam["right"], cam["up"]])
+    for x0, x1, y0, y1 in [(0, 40, 0, 30), (3, 9, 20, 30), (17, 23, 12, 18), (39, 40, 0, 1), (0, 1, 29, 30)]:
+        t, sg = 2.0, 0.7
+        c, ax = q.frustum_box(cam, [x0], [x1], [y0], [y1], [t], [sg])
+        # continuous tangent-plane rectangle through the extreme pixel centers
+        xa, _ = q.pixel_coords(cam, x0, 0)
+        xb, _ = q.pixel_coords(cam, x1 - 1, 0)
+        _, ya = q.pixel_coords(cam, 0, y1 - 1)
+        _, yb = q.pixel_coords(cam, 0, y0)
+        n = 20000
+        x = rng.uniform(min(xa, xb), max(xa, xb), n)
+        y = rng.uniform(min(ya, yb), max(ya, yb), n)
+        # include every combination of the x and y extremes (ends and the
+        # point nearest the axis) at both distances
+        cx = [xa, xb, np.clip(0.0, min(xa, xb), max(xa, xb))]
+        cy = [ya, yb, np.clip(0.0, min(ya, yb), max(ya, yb))]
+        ex = np.array([a for a in cx for _ in cy] * 2)
+        ey = np.array([b for _ in cx for b in cy] * 2)
+        es = np.repeat([t, t + sg], 9)
+        s = rng.uniform(t, t + sg, n)
+        x, y, s = np.concatenate([x, ex]), np.concatenate([y, ey]), np.concatenate([s, es])
+        d = cam["forward"][None] + x[:, None] * cam["right"][None] + y[:, None] * cam["up"][None]
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        p = cam["eye"][None] + s[:, None] * d
+        # coordinates in the box's own axes
+        half = np.linalg.norm(ax[0], axis=1)
+        u = ((p - c[0][None]) @ frame.T) / half[None]
+        assert np.all(np.abs(u) <= 1.0 + 1e-12), np.abs(u).max()
+        assert np.all(u.max(axis=0) >= 1.0 - 1e-9) and np.all(u.min(axis=0) <= -1.0 + 1e-9), (u.min(0), u.max(0))
+
+
+def test_frustum_cast_octahedron_closed_form():
+    """Frustum casting on the exact octahedron: every pixel's hit is the
+    closed-form first intersection up to delta, and every ray through the
+    solid hits (the solid is far thicker than delta)."""
+    R = 0.6
+    net = wl.octahedron_mlp(R)
+    cam = wl.camera(32, 24, 5, fov_deg=30.0)
+    delta = 1e-3
+    th, steps = q.cast_frusta(net, cam, tiles=(4, 4), delta=delta)
+    o, d = wl.camera_rays(32, 24, 5, fov_deg=30.0)
+    n_hit = 0
+    for i in range(o.shape[0]):
+        p, r = o[i].astype(np.float64), q.pixel_dirs(cam, i % 32, i // 32).reshape(3)
+        ts = math.inf
+        bps = sorted(tt for tt in (-p / np.where(r == 0, np.inf, r)) if tt > 0.0) + [20.0]
+        prev = 0.0
+        g = lambda tt: np.abs(p + tt * r).sum() - R
+        for t1 in bps:
+            if (g(prev) > 0) != (g(t1) > 0):
+                ts = prev + g(prev) * (t1 - prev) / (g(prev) - g(t1))
+                break
+            prev = t1
+        if math.isinf(ts):
+            assert math.isinf(th[i]), i
+        else:
+            n_hit += 1
+            assert ts - delta - 1e-9 <= th[i] <= ts + 1e-9, (i, th[i], ts)
+    assert n_hit > 50
+    assert steps.min() >= 1
+
+
+@pytest.mark.parametrize("netname", ["tiny", "elu"])
+def test_frustum_cast_matches_ray_cast(netname):
+    """On random networks the frustum caster and the per-ray caster return the
+    same hits up to the delta contract (Section 4.1): the same hit/miss
+    decision and hit distances within 2 delta, and every frustum result,
+    where they differ, passes the FP64 contract check."""
+    from parity import ray_contract_violations
+    net = wl.tiny_net(0) if netname == "tiny" else wl.he_normal_mlp([3, 32, 32, 1], 41, act="elu", bias=-0.3)
+    cam = wl.camera(24, 24, 7)
+    delta = 1e-3
+    th, _ = q.cast_frusta(net, cam, tiles=(4, 4), delta=delta)
+    o, d = wl.camera_rays(24, 24, 7)
+    tr, _ = q.cast_rays(net, o.astype(np.float64), q.pixel_dirs(cam, np.arange(576) % 24, np.arange(576) // 24),
+                        delta=delta)
+    agree = np.isfinite(th) == np.isfinite(tr)
+    both = np.isfinite(th) & np.isfinite(tr)
+    near = np.abs(np.where(both, th, 0.0) - np.where(both, tr, 0.0)) <= 2 * delta + 1e-9
+    assert agree.mean() >= 0.98 and near.mean() >= 0.98
+    differ = np.flatnonzero(~agree | ~near)
+    dirs = q.pixel_dirs(cam, np.arange(576) % 24, np.arange(576) // 24)
+    bad = ray_contract_violations(net, np.broadcast_to(cam["eye"], (576, 3)), dirs, th, differ, delta, 1e-9)
+    assert not bad, bad[:5]

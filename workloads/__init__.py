@@ -164,11 +164,14 @@ def points(n, seed, dom=1.0):
     return _f32(rng.uniform(-dom, dom, (n, 3)))
 
 
-def camera_rays(width, height, seed, radius=3.5, fov_deg=60.0):
-    """Pinhole camera rays: eye uniform on a sphere of the given radius, looking
-    at the origin, up = +z, vertical field of view fov_deg.  Returns (origin,
-    direction) float32 [height*width, 3] with unit-length directions (pixel
-    centers, row-major from the top row)."""
+def camera(width, height, seed, radius=3.5, fov_deg=60.0):
+    """A pinhole camera: eye uniform on a sphere of the given radius, looking at
+    the origin, up = +z, vertical field of view fov_deg.  Returns a dict with
+    the FP64 eye, orthonormal forward / right / up vectors, the tangents of the
+    half fields of view (tan_x, tan_y) and the image size.  Pixel (px, py)
+    (row-major from the top row) looks along normalize(forward + x right +
+    y up) with x = (2 (px + 0.5) / width - 1) tan_x and
+    y = (1 - 2 (py + 0.5) / height) tan_y."""
     rng = np.random.default_rng(seed)
     v = rng.standard_normal(3)
     eye = radius * v / np.linalg.norm(v)
@@ -180,14 +183,23 @@ def camera_rays(width, height, seed, radius=3.5, fov_deg=60.0):
     right /= np.linalg.norm(right)
     true_up = np.cross(right, fwd)
     th = math.tan(math.radians(fov_deg) / 2.0)
-    aspect = width / height
-    ys = (1.0 - 2.0 * (np.arange(height) + 0.5) / height) * th
-    xs = (2.0 * (np.arange(width) + 0.5) / width - 1.0) * th * aspect
+    return {"eye": eye, "forward": fwd, "right": right, "up": true_up, "tan_x": th * width / height, "tan_y": th,
+            "width": int(width), "height": int(height)}
+
+
+def camera_rays(width, height, seed, radius=3.5, fov_deg=60.0):
+    """The rays of :func:`camera`'s pixels: (origin, direction) float32
+    [height*width, 3] with unit-length directions (pixel centers, row-major
+    from the top row)."""
+    cam = camera(width, height, seed, radius, fov_deg)
+    ys = (1.0 - 2.0 * (np.arange(height) + 0.5) / height) * cam["tan_y"]
+    xs = (2.0 * (np.arange(width) + 0.5) / width - 1.0) * cam["tan_x"]
     X, Y = np.meshgrid(xs, ys)
-    d = fwd[None, None, :] + X[..., None] * right[None, None, :] + Y[..., None] * true_up[None, None, :]
+    d = cam["forward"][None, None, :] + X[..., None] * cam["right"][None, None, :] + \
+        Y[..., None] * cam["up"][None, None, :]
     d = d.reshape(-1, 3)
     d /= np.linalg.norm(d, axis=1, keepdims=True)
-    o = np.broadcast_to(eye, d.shape)
+    o = np.broadcast_to(cam["eye"], d.shape)
     return _f32(o), _f32(d)
 
 
