@@ -275,6 +275,60 @@ typedef struct {
 } spk_ray_params;
 
 /*
+ * Frustum ray casting (Section 4.3; Appendix B).  A pinhole camera: pixel
+ * (px, py), row-major from the top row, looks from eye along
+ * normalize(forward + x right + y up) with
+ *   x = (2 (px + 0.5) / width - 1) tan_x,  y = (1 - 2 (py + 0.5) / height) tan_y.
+ * forward, right, up must be orthonormal (dot products within 1e-6).
+ */
+typedef struct {
+  float eye[3];
+  float forward[3];
+  float right[3];
+  float up[3];
+  float tan_x, tan_y;   /* tangents of the half fields of view (> 0)            */
+  int32_t width, height;
+} spk_camera;
+
+typedef struct {
+  int64_t frustum_steps;     /* frustum boxes bounded                           */
+  int64_t rays_handed_off;   /* pixels continued as single rays                 */
+  int64_t ray_iterations;    /* Procedure 2 iterations of those rays            */
+  int32_t rounds;            /* frustum rounds                                  */
+  int32_t reserved;
+} spk_frustum_stats;
+
+/*
+ * spk_cast_frusta: cast the camera's width x height pixel rays against the
+ * level set inside the domain [-1,1]^3 by marching a tiles_x x tiles_y grid
+ * of coarse frusta (pixel rectangles) forward.  Each step bounds f over the
+ * oriented camera-frame box of the frustum between distances t and t + sigma
+ * (extended to the rays' spherical front); the step is taken (t += safety
+ * sigma, sigma *= eta_plus) when the box misses the domain or f is bounded
+ * away from zero on it, else sigma *= eta_minus, and a frustum whose width at
+ * t + sigma exceeds 2 sigma (or with sigma < delta) splits in half along its
+ * wider image direction.  A single-pixel frustum continues as Procedure 2
+ * from its t over the ray's chord of the domain.  Frusta start at the
+ * distance of the domain's bounding sphere.
+ *   params   delta, sigma0, eta_minus, eta_plus, safety, max_iters (of the
+ *            per-pixel rays) and flags as in spk_cast_rays; t_max and
+ *            clip_to_domain are not used.
+ *   box_opts policy, k, prec of the frustum-box bounds; its
+ *            SPK_FLAG_NO_ROUNDING_BOUND bit must equal params->flags'.
+ *   t_hit    dev [height * width]: distance from the eye along the pixel's
+ *            unit ray to its hit, +inf for none.
+ *   iters    dev int32 [height * width] nullable: frustum steps the pixel
+ *            took part in plus its ray iterations.
+ *   stats    host nullable.
+ * The call is synchronous (one host round trip per frustum round) and takes
+ * its buffers (about 60 bytes per pixel) stream-ordered within the context's
+ * workspace limit.
+ */
+spk_status spk_cast_frusta(spk_ctx* ctx, const spk_net* net, const spk_ray_params* params,
+                           const spk_bound_opts* box_opts, const spk_camera* cam, int32_t tiles_x, int32_t tiles_y,
+                           float* t_hit, int32_t* iters, spk_frustum_stats* stats);
+
+/*
  * spk_cast_rays: Procedure 2 for n rays (origin, dir dev [n][3]; dir unit
  * length).  Segment bounds use affine-fixed (the paper's ray-casting choice).
  *   t_hit  dev [n]: first t with a sign change within delta, +inf for no hit.

@@ -404,8 +404,9 @@ def cast_frusta(net, cam, tiles=(16, 16), delta=1e-3, sigma0=1.0, eta_minus=0.5,
     t_far = float(np.linalg.norm(eye)) + R
     t_hit = np.full(W * H, np.inf)
     steps = np.zeros(W * H, dtype=np.int64)
-    xs = [int(round(i * W / tiles[0])) for i in range(tiles[0] + 1)]
-    ys = [int(round(j * H / tiles[1])) for j in range(tiles[1] + 1)]
+    # tile boundaries: i W / tiles rounded half up
+    xs = [(i * W + tiles[0] // 2) // tiles[0] for i in range(tiles[0] + 1)]
+    ys = [(j * H + tiles[1] // 2) // tiles[1] for j in range(tiles[1] + 1)]
     fr = [[xs[i], xs[i + 1], ys[j], ys[j + 1], t0, float(sigma0)]
           for j in range(tiles[1]) for i in range(tiles[0]) if xs[i + 1] > xs[i] and ys[j + 1] > ys[j]]
     hand_pix, hand_t = [], []

@@ -665,11 +665,11 @@ struct CallBuffers {
 // One chunk of queries through every level (see spk_closest_point); the
 // buffers are reused from chunk to chunk.
 struct CpBuffers {
-  CallBuffers B;
   void *best = nullptr, *codes = nullptr, *qidx = nullptr, *ncodes = nullptr, *nqidx = nullptr, *labels = nullptr,
        *fpts = nullptr, *fvals = nullptr, *cnt = nullptr, *dcur = nullptr;
   size_t c_best = 0, c_codes = 0, c_qidx = 0, c_ncodes = 0, c_nqidx = 0, c_labels = 0, c_fpts = 0, c_fvals = 0,
          c_cnt = 0, c_dcur = 0;
+  CallBuffers B;   // last: destroyed first, while the pointers above are alive
 };
 
 static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
@@ -860,6 +860,163 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
     c0 += cn;
   }
   return check_hip(hipStreamSynchronize(ctx->stream));
+}
+
+// Frustum ray casting (Section 4.3; Appendix B); kernels in frustum.hip.
+spk_status spk_cast_frusta(spk_ctx* ctx, const spk_net* net, const spk_ray_params* params,
+                           const spk_bound_opts* box_opts, const spk_camera* cam, int32_t tiles_x, int32_t tiles_y,
+                           float* t_hit, int32_t* iters, spk_frustum_stats* stats) {
+  if (ctx == nullptr || net == nullptr || params == nullptr || cam == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(box_opts);
+  if (st != SPK_OK) return st;
+  const spk_ray_params& p = *params;
+  if (!(p.delta > 0.0f) || !(p.sigma0 > 0.0f) || !(p.eta_minus > 0.0f && p.eta_minus < 1.0f) ||
+      !(p.eta_plus >= 1.0f) || !(p.safety > 0.0f && p.safety <= 1.0f) || p.max_iters <= 0 ||
+      !isfinite(p.delta) || !isfinite(p.sigma0) || !isfinite(p.eta_plus))
+    return SPK_E_INVAL;
+  if (p.flags & ~(uint32_t)SPK_FLAG_NO_ROUNDING_BOUND) return SPK_E_INVAL;
+  // the boxes take the rays' arithmetic
+  if ((box_opts->flags & SPK_FLAG_NO_ROUNDING_BOUND) != (p.flags & SPK_FLAG_NO_ROUNDING_BOUND)) return SPK_E_INVAL;
+  if (cam->width <= 0 || cam->height <= 0 || cam->width > 16384 || cam->height > 16384) return SPK_E_INVAL;
+  if (tiles_x < 1 || tiles_y < 1 || tiles_x > cam->width || tiles_y > cam->height) return SPK_E_INVAL;
+  if (!(cam->tan_x > 0.0f) || !(cam->tan_y > 0.0f) || !isfinite(cam->tan_x) || !isfinite(cam->tan_y))
+    return SPK_E_INVAL;
+  FrRound R = {};
+  const float* vin[4] = {cam->eye, cam->forward, cam->right, cam->up};
+  double* vout[4] = {R.cam.eye, R.cam.F, R.cam.Rt, R.cam.U};
+  for (int v = 0; v < 4; ++v)
+    for (int d = 0; d < 3; ++d) {
+      if (!isfinite(vin[v][d])) return SPK_E_INVAL;
+      vout[v][d] = (double)vin[v][d];
+    }
+  // the box construction takes forward, right, up as an orthonormal frame
+  const double* fr[3] = {R.cam.F, R.cam.Rt, R.cam.U};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const double dot = fr[a][0] * fr[b][0] + fr[a][1] * fr[b][1] + fr[a][2] * fr[b][2];
+      if (fabs(dot - (a == b ? 1.0 : 0.0)) > 1e-6) return SPK_E_INVAL;
+    }
+  if (t_hit == nullptr) return SPK_E_INVAL;
+  R.cam.tan_x = cam->tan_x;
+  R.cam.tan_y = cam->tan_y;
+  R.cam.width = cam->width;
+  R.cam.height = cam->height;
+  R.p = p;
+  const double dist = sqrt(R.cam.eye[0] * R.cam.eye[0] + R.cam.eye[1] * R.cam.eye[1] + R.cam.eye[2] * R.cam.eye[2]);
+  // the domain [-1,1]^3 lies in the ball of radius sqrt(3)
+  R.t0 = (float)fmax(0.0, dist - 1.7320508075688772 - 1e-6);
+  R.t_far = dist + 1.7320508075688772 + 1e-6;
+  R.sigma0 = p.sigma0;
+  R.t_hit = t_hit;
+  R.iters = iters;
+  const int64_t npix = (int64_t)cam->width * cam->height;
+  const int64_t n0 = (int64_t)tiles_x * tiles_y;
+  R.cap = npix;
+
+  // the buffer pointers outlive B, whose destructor frees them
+  void *cur = nullptr, *next = nullptr, *cen = nullptr, *axs = nullptr, *miss = nullptr, *lo = nullptr, *hi = nullptr,
+       *hp = nullptr, *ht = nullptr, *hs = nullptr, *cnt = nullptr, *org = nullptr, *dir = nullptr, *trel = nullptr,
+       *itr = nullptr;
+  size_t c_cur = 0, c_next = 0, c_cen = 0, c_axs = 0, c_miss = 0, c_lo = 0, c_hi = 0, c_hp = 0, c_ht = 0, c_hs = 0,
+         c_cnt = 0, c_org = 0, c_dir = 0, c_trel = 0, c_itr = 0;
+  CallBuffers B;
+  B.limit = ctx->workspace_limit;
+  B.stream = ctx->stream;
+  B.peak = &ctx->ws_peak;
+#define SPK_FR_ENSURE(ptr, cap, bytes)              \
+  do {                                              \
+    spk_status e_ = B.ensure(&(ptr), cap, (bytes)); \
+    if (e_ != SPK_OK) return e_;                    \
+  } while (0)
+  SPK_FR_ENSURE(cur, c_cur, (size_t)npix * sizeof(Frustum));
+  SPK_FR_ENSURE(next, c_next, (size_t)npix * sizeof(Frustum));
+  SPK_FR_ENSURE(hp, c_hp, (size_t)npix * 8);
+  SPK_FR_ENSURE(ht, c_ht, (size_t)npix * 4);
+  SPK_FR_ENSURE(hs, c_hs, (size_t)npix * 4);
+  SPK_FR_ENSURE(cnt, c_cnt, 256);
+  R.cur = (Frustum*)cur;
+  R.next = (Frustum*)next;
+  R.hand_pix = (int64_t*)hp;
+  R.hand_t = (float*)ht;
+  R.hand_steps = (int32_t*)hs;
+  R.counts = (unsigned long long*)cnt;
+  st = launch_fr_zero(R.counts, 3, ctx->stream);
+  if (st != SPK_OK) return st;
+  st = launch_fr_init(R, tiles_x, tiles_y, ctx->stream);
+  if (st != SPK_OK) return st;
+  int64_t m = n0, total_steps = 0;
+  int32_t rounds = 0;
+  unsigned long long hc[3] = {0ull, 0ull, 0ull};
+  while (m > 0) {
+    if (++rounds > 1000000) return SPK_E_DEVICE;   // not reached: every round makes progress
+    SPK_FR_ENSURE(cen, c_cen, (size_t)m * 12);
+    SPK_FR_ENSURE(axs, c_axs, (size_t)m * 36);
+    SPK_FR_ENSURE(miss, c_miss, (size_t)m);
+    SPK_FR_ENSURE(lo, c_lo, (size_t)m * 4);
+    SPK_FR_ENSURE(hi, c_hi, (size_t)m * 4);
+    R.center = (float*)cen;
+    R.axes = (float*)axs;
+    R.miss = (uint8_t*)miss;
+    R.lo = (const float*)lo;
+    R.hi = (const float*)hi;
+    st = launch_fr_box(R, m, ctx->stream);
+    if (st != SPK_OK) return st;
+    BoundJob job = {};
+    job.n = m;
+    job.mode = IN_GENERAL;
+    job.s = 3;
+    job.policy = box_opts->policy;
+    job.k = box_opts->k;
+    job.prec = box_opts->prec;
+    job.rigorous = (p.flags & SPK_FLAG_NO_ROUNDING_BOUND) ? 0 : 1;
+    job.a = (const float*)cen;
+    job.b = (const float*)axs;
+    job.lo = (float*)lo;
+    job.hi = (float*)hi;
+    st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+    st = launch_fr_update(R, m, ctx->stream);
+    if (st != SPK_OK) return st;
+    total_steps += m;
+    if (hipMemcpyAsync(hc, R.counts, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return SPK_E_DEVICE;
+    m = (int64_t)hc[0];
+    if (m > npix || (int64_t)hc[1] > npix) return SPK_E_DEVICE;   // disjoint pixel sets: cannot happen
+    std::swap(R.cur, R.next);
+  }
+  const int64_t nh = (int64_t)hc[1];
+  if (nh > 0) {
+    SPK_FR_ENSURE(org, c_org, (size_t)nh * 12);
+    SPK_FR_ENSURE(dir, c_dir, (size_t)nh * 12);
+    SPK_FR_ENSURE(trel, c_trel, (size_t)nh * 4);
+    SPK_FR_ENSURE(itr, c_itr, (size_t)nh * 4);
+    st = launch_fr_rays(R, nh, (float*)org, (float*)dir, ctx->stream);
+    if (st != SPK_OK) return st;
+    spk_ray_params rp = p;
+    rp.clip_to_domain = 1;
+    void* counter = nullptr;
+    st = ctx_scratch(ctx, 256, &counter);
+    if (st != SPK_OK) return st;
+    st = launch_rays(net, rp, nh, (const float*)org, (const float*)dir, (float*)trel, (int32_t*)itr,
+                     (unsigned long long*)counter, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+    st = launch_fr_scatter(R, nh, (const float*)trel, (const int32_t*)itr, ctx->stream);
+    if (st != SPK_OK) return st;
+  }
+#undef SPK_FR_ENSURE
+  if (stats != nullptr) {
+    if (hipMemcpyAsync(hc, R.counts, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess) return SPK_E_DEVICE;
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return SPK_E_DEVICE;
+  if (stats != nullptr) {
+    stats->frustum_steps = total_steps;
+    stats->rays_handed_off = nh;
+    stats->ray_iterations = (int64_t)hc[2];
+    stats->rounds = rounds;
+    stats->reserved = 0;
+  }
+  return SPK_OK;
 }
 
 spk_status spk_eval_points(spk_ctx* ctx, const spk_net* net, int64_t n, const float* x, float* f) {

@@ -131,6 +131,41 @@ struct CpDive {
   float* point;              // [n][3] candidates
 };
 
+// Frustum ray casting (frustum.hip).
+struct Frustum {
+  int32_t x0, x1, y0, y1;   // pixel rectangle [x0, x1) x [y0, y1)
+  float t, sigma;
+  int32_t steps;            // bound steps taken by the frustum and its ancestors
+  int32_t pad;
+};
+
+struct FrCam {
+  double eye[3], F[3], Rt[3], U[3];   // camera frame (forward, right, up)
+  double tan_x, tan_y;
+  int32_t width, height;
+};
+
+struct FrRound {
+  FrCam cam;
+  spk_ray_params p;
+  float t0, sigma0;
+  double t_far;
+  Frustum* cur;              // [m] live frusta
+  Frustum* next;             // [cap] next round
+  int64_t cap;               // width * height
+  float* center;             // [m][3] boxes
+  float* axes;               // [m][3][3]
+  uint8_t* miss;             // [m] box misses the domain
+  const float* lo;           // [m] bound of f over the box
+  const float* hi;
+  int64_t* hand_pix;         // [cap] handed-off pixels
+  float* hand_t;
+  int32_t* hand_steps;
+  unsigned long long* counts;   // [0] next frusta, [1] handed-off pixels, [2] ray iterations
+  float* t_hit;              // [height * width]
+  int32_t* iters;            // nullable
+};
+
 }  // namespace spk
 
 struct spk_net {
@@ -194,6 +229,12 @@ spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, c
 spk_status launch_cp_init(int64_t n, uint64_t* codes, uint32_t* qidx, unsigned* best, float* point,
                           hipStream_t stream, int num_cus);
 spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t stream, int num_cus);
+spk_status launch_fr_init(const FrRound& R, int tiles_x, int tiles_y, hipStream_t stream);
+spk_status launch_fr_box(const FrRound& R, int64_t m, hipStream_t stream);
+spk_status launch_fr_update(const FrRound& R, int64_t m, hipStream_t stream);
+spk_status launch_fr_zero(unsigned long long* counts, int n, hipStream_t stream);
+spk_status launch_fr_rays(const FrRound& R, int64_t n, float* origin, float* dir, hipStream_t stream);
+spk_status launch_fr_scatter(const FrRound& R, int64_t n, const float* trel, const int32_t* itr, hipStream_t stream);
 spk_status launch_cp_dive_init(int64_t n, uint64_t* cur, hipStream_t stream, int num_cus);
 spk_status launch_cp_dive_children(const CpDive& D, hipStream_t stream, int num_cus);
 spk_status launch_cp_dive_pick(const CpDive& D, hipStream_t stream, int num_cus);

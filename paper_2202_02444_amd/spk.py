@@ -23,7 +23,8 @@ UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
-           "spk_subdivide_frontier", "spk_subdivide_frontier_noalloc", "spk_cast_rays", "spk_eval_points", "spk_closest_point",
+           "spk_subdivide_frontier", "spk_subdivide_frontier_noalloc", "spk_cast_rays", "spk_cast_frusta",
+           "spk_eval_points", "spk_closest_point",
            "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
            "spk_batch_destroy", "spk_server_create", "spk_server_submit", "spk_server_poll",
            "spk_server_pending", "spk_server_destroy")
@@ -64,6 +65,17 @@ class BoundAux(ctypes.Structure):
 class DeviceStatus(ctypes.Structure):
     _fields_ = [("nonfinite_inputs", ctypes.c_int64), ("nospc", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("need_children", ctypes.c_int64), ("need_leaves", ctypes.c_int64)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("forward", ctypes.c_float * 3), ("right", ctypes.c_float * 3),
+                ("up", ctypes.c_float * 3), ("tan_x", ctypes.c_float), ("tan_y", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class FrustumStats(ctypes.Structure):
+    _fields_ = [("frustum_steps", ctypes.c_int64), ("rays_handed_off", ctypes.c_int64),
+                ("ray_iterations", ctypes.c_int64), ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class TreeParams(ctypes.Structure):
@@ -114,6 +126,8 @@ def lib():
         L.spk_subdivide_frontier_noalloc.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
+        L.spk_cast_frusta.argtypes = [vp, vp, ctypes.POINTER(RayParams), ctypes.POINTER(BoundOpts),
+                                      ctypes.POINTER(Camera), i32, i32, vp, vp, ctypes.POINTER(FrustumStats)]
         L.spk_eval_points.argtypes = [vp, vp, i64, vp, vp]
         L.spk_batch_create.argtypes = [vp, ctypes.POINTER(BoundOpts), i32, ctypes.POINTER(BatchItem),
                                        ctypes.POINTER(vp)]
@@ -321,6 +335,33 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
                              _ptr(direction, torch.float32, (n, 3), "direction"),
                              _ptr(t_hit, torch.float32, (n,), "t_hit"), _ptr(iters, torch.int32, (n,), "iters"))
     _check(st, "spk_cast_rays")
+
+
+def camera(cam):
+    """spk_camera from a dict with eye, forward, right, up, tan_x, tan_y, width,
+    height (e.g. workloads.camera)."""
+    f3 = ctypes.c_float * 3
+    return Camera(f3(*map(float, cam["eye"])), f3(*map(float, cam["forward"])), f3(*map(float, cam["right"])),
+                  f3(*map(float, cam["up"])), float(cam["tan_x"]), float(cam["tan_y"]), int(cam["width"]),
+                  int(cam["height"]))
+
+
+def cast_frusta(ctx, net, cam, t_hit, iters=None, tiles=(16, 16), policy="fixed", k=31, prec="f32", rigorous=True,
+                **params):
+    """spk_cast_frusta: t_hit [height * width] (and iters) for the camera's
+    pixel rays; returns the frustum statistics as a dict."""
+    import torch
+    c = camera(cam)
+    n = c.width * c.height
+    rp = ray_params(rigorous=rigorous, **params)
+    o = opts(policy, k, rigorous, prec)
+    stats = FrustumStats()
+    st = lib().spk_cast_frusta(ctx.handle, net.handle, ctypes.byref(rp), ctypes.byref(o), ctypes.byref(c),
+                               int(tiles[0]), int(tiles[1]), _ptr(t_hit, torch.float32, (n,), "t_hit"),
+                               _ptr(iters, torch.int32, (n,), "iters"), ctypes.byref(stats))
+    _check(st, "spk_cast_frusta")
+    return {"frustum_steps": int(stats.frustum_steps), "rays_handed_off": int(stats.rays_handed_off),
+            "ray_iterations": int(stats.ray_iterations), "rounds": int(stats.rounds)}
 
 
 def closest_point(ctx, net, q, point, dist=None, bound=None, max_level=8, policy="fixed", k=31,

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2202_02444_amd import spk
+import workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -130,6 +131,34 @@ def test_tree_and_ray_validation():
     assert spk.ray_params(rigorous=False).flags == spk.FLAG_NO_ROUNDING_BOUND and spk.ray_params().flags == 0
 
 
+def test_frustum_validation():
+    L = spk.lib()
+    cam = spk.camera(wl.camera(8, 6, 1))
+    rp = spk.ray_params()
+    o = spk.opts("fixed", 0)
+    st = spk.FrustumStats()
+    call = lambda r, oo, c, tx, ty, th: L.spk_cast_frusta(FAKE, FAKE, ctypes.byref(r), ctypes.byref(oo),
+                                                           ctypes.byref(c), tx, ty, th, None, ctypes.byref(st))
+    assert L.spk_cast_frusta(None, FAKE, ctypes.byref(rp), ctypes.byref(o), ctypes.byref(cam), 2, 2, FAKE, None,
+                             None) == spk.E_INVAL
+    assert call(rp, o, cam, 2, 2, None) == spk.E_INVAL                    # no output
+    assert call(rp, o, cam, 0, 2, FAKE) == spk.E_INVAL                    # no tiles
+    assert call(rp, o, cam, 9, 2, FAKE) == spk.E_INVAL                    # more tiles than pixels
+    paper = spk.opts("fixed", 0, rigorous=False)
+    assert call(rp, paper, cam, 2, 2, FAKE) == spk.E_INVAL                # arithmetic differs from the rays'
+    bad = spk.camera(wl.camera(8, 6, 1))
+    bad.right[0] += 1e-3                                                  # not orthonormal
+    assert call(rp, o, bad, 2, 2, FAKE) == spk.E_INVAL
+    bad = spk.camera(wl.camera(8, 6, 1))
+    bad.tan_x = 0.0
+    assert call(rp, o, bad, 2, 2, FAKE) == spk.E_INVAL
+    bad = spk.camera(wl.camera(8, 6, 1))
+    bad.width = 0
+    assert call(rp, o, bad, 1, 1, FAKE) == spk.E_INVAL
+    full = spk.opts("full", 0)
+    assert call(rp, full, cam, 2, 2, FAKE) == spk.E_UNSUPPORTED
+
+
 def test_closest_point_validation():
     L = spk.lib()
     o = spk.opts("fixed", 0)
@@ -178,7 +207,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     structs = {"spk_bound_opts": spk.BoundOpts, "spk_bound_aux": spk.BoundAux, "spk_tree_params": spk.TreeParams,
                "spk_ray_params": spk.RayParams, "spk_batch_item": spk.BatchItem, "spk_batch_class": spk.BatchClass,
                "spk_request": spk.Request, "spk_completion": spk.Completion,
-               "spk_device_status": spk.DeviceStatus}
+               "spk_device_status": spk.DeviceStatus, "spk_camera": spk.Camera,
+               "spk_frustum_stats": spk.FrustumStats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "spk.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
