@@ -109,6 +109,34 @@ def rays_extra(ctx, g, dev, side=512, seed=600):
     return out
 
 
+def frusta_extra(ctx, g, dev, side=512, seed=600, tiles=(16, 16)):
+    """Frustum ray casting (Section 4.3) of the same 512x512 blob view as the
+    ray extra: a 16x16 grid of coarse frusta, affine-truncate(31) boxes, in
+    the paper's arithmetic (FP32) and rounding-bounded (FP64 generator
+    products, which keep the small frustum boxes tight); rays/s, frustum
+    steps, handed-off pixels and the amortized bound evaluations per pixel
+    (frustum steps + ray iterations over the pixel count)."""
+    import torch
+    import workloads as wl
+    from paper_2202_02444_amd import spk
+    cam = wl.camera(side, side, seed)
+    n = side * side
+    th = torch.empty(n, device=dev)
+    it = torch.empty(n, dtype=torch.int32, device=dev)
+    out = {"pixels": n, "tiles": list(tiles)}
+    for name, rig, prec in (("paper", False, "f32"), ("rigorous_f64_boxes", True, "f64")):
+        spk.cast_frusta(ctx, g, cam, th, it, tiles=tiles, policy="truncate", k=K_KEEP, prec=prec, rigorous=rig)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = spk.cast_frusta(ctx, g, cam, th, it, tiles=tiles, policy="truncate", k=K_KEEP, prec=prec, rigorous=rig)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        st.update({"rays_per_s": n / dt, "seconds": dt, "hits": int(torch.isfinite(th).sum().item()),
+                   "amortized_steps_per_pixel": (st["frustum_steps"] + st["ray_iterations"]) / n})
+        out[name] = st
+    return out
+
+
 def closest_point_extra(ctx, dev, n=4096, max_level=10):
     """Closest point (Section 4.10) for n uniform queries, affine-fixed cells,
     on the tiny 3->32->32->1 ReLU net.  (On the 8x256 blob the affine-fixed
@@ -358,7 +386,7 @@ def main():
     ap.add_argument("--boxes", type=int, default=N_BOXES)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the octree / ray extra measurements")
-    ap.add_argument("--extras", default="octree,rays,closest,batched,precision,serving",
+    ap.add_argument("--extras", default="octree,rays,frusta,closest,batched,precision,serving",
                     help="comma-separated extra measurements to run")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -462,6 +490,9 @@ def main():
             extra["rays"] = rays_extra(ctx, g, dev)
             extra["rays_per_s"] = extra["rays"]["rays_per_s"]
             progress("rays done")
+        if "frusta" in which:
+            extra["frusta"] = frusta_extra(ctx, g, dev)
+            progress("frusta done")
         if "closest" in which:
             extra["closest_point"] = closest_point_extra(ctx, dev)
             progress("closest point done")

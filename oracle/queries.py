@@ -381,7 +381,7 @@ def frustum_box(cam, x0, x1, y0, y1, t, sigma):
 
 
 def cast_frusta(net, cam, tiles=(16, 16), delta=1e-3, sigma0=1.0, eta_minus=0.5, eta_plus=1.5, safety=0.98,
-                max_iters=100000, policy="fixed", k=31):
+                max_iters=100000, policy="truncate", k=31):
     """Frustum ray casting of the camera's image (Section 4.3): a tiles[0] x
     tiles[1] grid of coarse frusta over the pixels marches forward in steps
     like CastRay, each step bounding f over the oriented box of the frustum

@@ -346,7 +346,7 @@ def camera(cam):
                   int(cam["height"]))
 
 
-def cast_frusta(ctx, net, cam, t_hit, iters=None, tiles=(16, 16), policy="fixed", k=31, prec="f32", rigorous=True,
+def cast_frusta(ctx, net, cam, t_hit, iters=None, tiles=(16, 16), policy="truncate", k=31, prec="f32", rigorous=True,
                 **params):
     """spk_cast_frusta: t_hit [height * width] (and iters) for the camera's
     pixel rays; returns the frustum statistics as a dict."""
