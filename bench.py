@@ -137,23 +137,31 @@ def frusta_extra(ctx, g, dev, side=512, seed=600, tiles=(16, 16)):
     return out
 
 
-def closest_point_extra(ctx, dev, n=4096, max_level=10):
+def closest_point_extra(ctx, dev, n=4096, max_level=10, n_blob=256, blob_level=6):
     """Closest point (Section 4.10) for n uniform queries, affine-fixed cells,
-    on the tiny 3->32->32->1 ReLU net.  (On the 8x256 blob the affine-fixed
-    bounds leave nearly every cell above level 8 UNKNOWN, so the exact search
-    visits a large part of the tree per query.)"""
+    on the tiny 3->32->32->1 ReLU net at level 10, and for n_blob queries on
+    the 8x256 blob at level 6 (affine-truncate(31) cells, paper arithmetic).
+    On the blob the bounds leave a thick band of UNKNOWN cells around the
+    surface (at level 8 about 12 % of all cells), and every such cell within
+    the query's distance bound must be visited, so the exact search costs
+    far more per query there."""
     import torch
     import workloads as wl
     from paper_2202_02444_amd import spk
-    g = spk.Net.from_spec(wl.tiny_net(0))
-    q = torch.from_numpy(wl.points(n, 501)).to(dev)
-    pt = torch.empty((n, 3), device=dev)
-    dist = torch.empty(n, device=dev)
-    t = time.perf_counter()
-    spk.closest_point(ctx, g, q, pt, dist, max_level=max_level, policy="fixed")
-    dt = time.perf_counter() - t
-    return {"net": "3->32->32->1 ReLU (tiny)", "queries": n, "max_level": max_level, "queries_per_s": n / dt,
-            "found": int(torch.isfinite(dist).sum().item())}
+    out = {}
+    for name, spec, nq, lvl, pol, rig in (("tiny", wl.tiny_net(0), n, max_level, "fixed", True),
+                                          ("blob8x256", wl.scale_net(1), n_blob, blob_level, "truncate", False)):
+        g = spk.Net.from_spec(spec)
+        q = torch.from_numpy(wl.points(nq, 501)).to(dev)
+        pt = torch.empty((nq, 3), device=dev)
+        dist = torch.empty(nq, device=dev)
+        t = time.perf_counter()
+        spk.closest_point(ctx, g, q, pt, dist, max_level=lvl, policy=pol, k=K_KEEP, rigorous=rig)
+        dt = time.perf_counter() - t
+        out[name] = {"queries": nq, "max_level": lvl, "policy": pol, "rigorous": rig, "queries_per_s": nq / dt,
+                     "found": int(torch.isfinite(dist).sum().item())}
+    out["queries_per_s"] = out["tiny"]["queries_per_s"]
+    return out
 
 
 def batched_extra(ctx, dev, policy="truncate", k=K_KEEP):
@@ -470,10 +478,11 @@ def main():
         which = set(args.extras.split(","))
         if "octree" in which:
             # depth 10 in the paper's arithmetic (rounding ignored, as in the
-            # paper); with the rounding bound the frontier of this net grows
-            # past the 64M-cell cap at depth 10 (the FP32 rounding bound
-            # dominates the width of its smallest cells), so the rigorous tree
-            # is measured to depth 8
+            # paper); with the rounding bound in FP32 no cell of this net below
+            # level 6 is classified (the a-priori FP32 product rounding, carried
+            # through |W| over seven layers, exceeds the small cells' ranges),
+            # so the rigorous tree runs with FP64 generator products, to depth 8
+            # (at depth 10 its frontier passes 50M cells)
             t = time.perf_counter()
             levels, leaves = spk.build_octree(ctx, g, 10, "truncate", K_KEEP, rigorous=False)
             torch.cuda.synchronize()
@@ -481,10 +490,10 @@ def main():
             extra["octree_leaves"] = int(leaves.shape[0])
             extra["octree_frontier"] = [lv["n"] for lv in levels]
             t = time.perf_counter()
-            levels, leaves = spk.build_octree(ctx, g, 8, "truncate", K_KEEP)
+            levels, leaves = spk.build_octree(ctx, g, 8, "truncate", K_KEEP, prec="f64")
             torch.cuda.synchronize()
-            extra["octree_rigorous_depth8_s"] = time.perf_counter() - t
-            extra["octree_rigorous_frontier"] = [lv["n"] for lv in levels]
+            extra["octree_rigorous_f64_depth8_s"] = time.perf_counter() - t
+            extra["octree_rigorous_f64_frontier"] = [lv["n"] for lv in levels]
             progress("octree done")
         if "rays" in which:
             extra["rays"] = rays_extra(ctx, g, dev)

@@ -244,3 +244,72 @@ def test_precision_soundness_1e7_points(ctx):
     print("soundness: %d random points and %d corners inside the FP32, BF16 and FP16 bounds (%.0f s)" % (
         n_pts, f.size, time.perf_counter() - t0), flush=True)
     assert n_pts >= 10_000_000
+
+
+def test_octree_depth10_sampled(ctx):
+    """The bench's depth-10 octree of the 8x256 blob (paper arithmetic,
+    affine-truncate(31) cells), driven round by round through the C ABI and
+    checked by sampling: at every level sampled UNKNOWN and sampled classified
+    cells carry the oracle's label (outside the ambiguity band), the children
+    are exactly 8 per UNKNOWN cell, the POSITIVE / NEGATIVE cells of all levels
+    and the depth-10 leaves tile the domain exactly, and sampled leaves are
+    UNKNOWN for the oracle."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = wl.scale_net(1)
+    g = spk.Net.from_spec(net)
+    S = s_net(net)
+    rng = np.random.default_rng(77)
+    dev = torch.device("cuda")
+    depth = 10
+    dom = ((-1.0,) * 3, (1.0,) * 3)
+    cells = torch.zeros(1, dtype=torch.int64, device=dev)
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    volume = 0.0
+    bad, checked = [], 0
+
+    def check(codes, level, want_unknown):
+        nonlocal checked
+        if codes.size == 0:
+            return
+        lo, hi = oq.cell_bounds(codes, level, *dom)
+        _, _, ly, hy = omlp.bound_boxes(net, lo, hi, "truncate", 31)
+        lab_o = oracle_labels(ly, hy)
+        amb = label_ambiguous(ly, hy, S, 4e-6 * (np.abs(ly) + np.abs(hy)))
+        for j in range(codes.size):
+            checked += 1
+            ok = amb[j] or ((lab_o[j] == spk.UNKNOWN) == want_unknown)
+            if not ok:
+                bad.append((level, int(codes[j]), int(lab_o[j]), want_unknown))
+
+    for level in range(depth + 1):
+        n = cells.shape[0]
+        at_max = level == depth
+        capc = 0 if at_max else 8 * n
+        children = torch.empty(max(capc, 1), dtype=torch.int64, device=dev)
+        leaves = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        spk.subdivide_frontier(ctx, g, level, cells, children[:capc] if capc else None,
+                               leaves[:n] if at_max else None, counts, depth, "truncate", 31, rigorous=False)
+        ctx.sync()
+        c = counts.cpu().numpy()
+        volume += float(c[2] + c[3]) * 8.0 ** -level
+        codes = cells.cpu().numpy().astype(np.uint64)
+        if at_max:
+            lv = np.sort(leaves[:c[1]].cpu().numpy().astype(np.uint64))
+            assert c[1] + c[2] + c[3] == n
+            volume += float(c[1]) * 8.0 ** -depth
+            check(lv[rng.choice(lv.size, size=min(192, lv.size), replace=False)], level, True)
+            break
+        kids = np.sort(children[:c[0]].cpu().numpy().astype(np.uint64))
+        assert c[0] % 8 == 0 and c[0] // 8 + c[2] + c[3] == n
+        parents = np.unique(kids >> np.uint64(3))
+        assert parents.size == c[0] // 8
+        unk = np.isin(codes, parents)
+        known = np.flatnonzero(~unk)
+        check(codes[rng.choice(np.flatnonzero(unk), size=min(48, int(unk.sum())), replace=False)], level, True)
+        if known.size:
+            check(codes[rng.choice(known, size=min(48, known.size), replace=False)], level, False)
+        cells = children[:c[0]].clone()
+    assert volume == 1.0, volume
+    assert checked > 500
+    assert not bad, bad[:5]
