@@ -362,11 +362,13 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
                              float* bound);
 
 /*
- * Batched bounds over many networks (Procedure 1 for each network's boxes).
- * The batch groups its networks into classes (hidden width x activation),
- * runs one persistent work-queue kernel per class and captures all of them
- * once in a HIP graph: spk_batch_launch is a single graph launch that
- * classifies every network's boxes, however uneven the box counts.
+ * Batched bounds over many networks (Procedure 1 for each network's boxes,
+ * and for frontier items one Procedure 3 round).  The batch groups its
+ * networks into classes (hidden width x activation), runs one persistent
+ * work-queue kernel per class and captures all of them once in a HIP graph,
+ * followed by one compaction kernel over every frontier item:
+ * spk_batch_launch is a single graph launch that classifies every network's
+ * boxes or cells and compacts every frontier, however uneven the sizes.
  *
  *   spk_batch_create  items host [n_items] (read during the call); the nets
  *                     must live on the context's device and stay alive
@@ -386,12 +388,29 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
  */
 typedef struct {
   const spk_net* net;
-  int64_t n;               /* boxes of this network (>= 0)                 */
-  const float* box_lo;     /* dev [n][3]                                    */
-  const float* box_hi;     /* dev [n][3]                                    */
+  int64_t n;               /* boxes (or cells) of this network (>= 0)       */
+  const float* box_lo;     /* dev [n][3] (box items)                        */
+  const float* box_hi;     /* dev [n][3] (box items)                        */
   uint8_t* label;          /* dev [n] uint8 class                           */
   float* lo;               /* dev [n] nullable                              */
   float* hi;               /* dev [n] nullable                              */
+  /* Frontier items (Procedure 3 rounds): with cells non-null the n boxes
+   * are the Morton cells of `level` in tree (arity 8), and the graph also
+   * compacts the round as spk_subdivide_frontier does: UNKNOWN cells below
+   * tree.max_level emit their 8 children (at most cap_children written),
+   * UNKNOWN cells at max_level go to leaves (at most cap_leaves);
+   * counts dev int64 [4] = {children, leaves, positive, negative}, the
+   * required sizes when a capacity is exceeded.  A batch created without
+   * frontier items takes none later. */
+  const uint64_t* cells;   /* dev [n] nullable: a box item                  */
+  int32_t level;
+  int32_t reserved;
+  spk_tree_params tree;
+  uint64_t* children;      /* dev [cap_children] nullable if cap is 0       */
+  int64_t cap_children;
+  uint64_t* leaves;        /* dev [cap_leaves] nullable if cap is 0         */
+  int64_t cap_leaves;
+  int64_t* counts;         /* dev [4] (frontier items)                      */
 } spk_batch_item;
 
 typedef struct spk_batch spk_batch;

@@ -135,6 +135,9 @@ struct spk_batch {
   float graph_ms = 0.0f;           // tuned time of one graph launch
   hipEvent_t last = nullptr;       // recorded after every spk_batch_launch
   bool held = false;               // the batch counts as a holder of its networks
+  bool frontier = false;           // frontier items: the graph also compacts
+  size_t off_compact = 0, off_cprefix = 0;   // CompactItem [n_items], chunk prefix [n_items + 1]
+  int compact_blocks = 0;
 };
 
 namespace {
@@ -155,7 +158,19 @@ BatchArgs class_args(const spk_batch* b, int c) {
 // Argument checks that read nothing but the item itself.
 spk_status valid_item(const spk_batch_item& it) {
   if (it.net == nullptr || it.n < 0) return SPK_E_INVAL;
-  if (it.n > 0 && (it.box_lo == nullptr || it.box_hi == nullptr || it.label == nullptr)) return SPK_E_INVAL;
+  if (it.cells == nullptr) {
+    if (it.n > 0 && (it.box_lo == nullptr || it.box_hi == nullptr || it.label == nullptr)) return SPK_E_INVAL;
+    return SPK_OK;
+  }
+  const spk_tree_params& t = it.tree;
+  if (t.arity != 8) return SPK_E_UNSUPPORTED;
+  if (t.max_level < 0 || t.max_level > 20 || it.level < 0 || it.level > t.max_level) return SPK_E_INVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(t.dom_lo[d] < t.dom_hi[d]) || !isfinite(t.dom_lo[d]) || !isfinite(t.dom_hi[d])) return SPK_E_INVAL;
+  if (it.counts == nullptr || it.cap_children < 0 || it.cap_leaves < 0) return SPK_E_INVAL;
+  if ((it.cap_children > 0 && it.children == nullptr) || (it.cap_leaves > 0 && it.leaves == nullptr))
+    return SPK_E_INVAL;
+  if (it.n > 0 && it.label == nullptr) return SPK_E_INVAL;
   return SPK_OK;
 }
 
@@ -172,7 +187,7 @@ spk_status write_descriptors(spk_batch* b, const spk_batch_item* items, hipStrea
       nd[j] = it.net->dev;
       spk::BoundJob job = {};
       job.n = it.n;
-      job.mode = spk::IN_AABB;
+      job.mode = it.cells ? spk::IN_CELL : spk::IN_AABB;
       job.s = 3;
       job.policy = b->opts.policy;
       job.k = b->opts.k;
@@ -180,6 +195,12 @@ spk_status write_descriptors(spk_batch* b, const spk_batch_item* items, hipStrea
       job.prec = SPK_PREC_F32;
       job.a = it.box_lo;
       job.b = it.box_hi;
+      job.cells = it.cells;
+      job.level = it.level;
+      for (int d = 0; d < 3; ++d) {
+        job.dom_lo[d] = it.tree.dom_lo[d];
+        job.dom_hi[d] = it.tree.dom_hi[d];
+      }
       job.lo = it.lo;
       job.hi = it.hi;
       job.label = it.label;
@@ -187,6 +208,29 @@ spk_status write_descriptors(spk_batch* b, const spk_batch_item* items, hipStrea
       prefix[j + 1] = prefix[j] + (it.n + bpw_of(p.H) - 1) / bpw_of(p.H);
     }
     p.groups = prefix[p.items.size()];
+  }
+  if (b->frontier) {
+    // the compaction descriptors: one per item in item order, box items empty
+    spk::CompactItem* ci = (spk::CompactItem*)(img.data() + b->off_compact);
+    int64_t* cp = (int64_t*)(img.data() + b->off_cprefix);
+    cp[0] = 0;
+    for (size_t i = 0; i < b->nets.size(); ++i) {
+      const spk_batch_item& it = items[i];
+      spk::CompactItem c = {};
+      if (it.cells) {
+        c.labels = it.label;
+        c.cells = it.cells;
+        c.n = it.n;
+        c.at_max = it.level == it.tree.max_level ? 1 : 0;
+        c.children = it.children;
+        c.cap_children = it.cap_children;
+        c.leaves = it.leaves;
+        c.cap_leaves = it.cap_leaves;
+        c.counts = (unsigned long long*)it.counts;
+      }
+      ci[i] = c;
+      cp[i + 1] = cp[i] + (c.n + 63) / 64;
+    }
   }
   if (hipMemcpyAsync(b->dev, img.data(), img.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
     return SPK_E_DEVICE;
@@ -236,6 +280,13 @@ spk_status capture(spk_batch* b) {
                    hipSuccess;
       if (ok) ok = hipEventRecord(b->ev[c], b->side[c]) == hipSuccess;
       if (ok) ok = hipStreamWaitEvent(cs, b->ev[c], 0) == hipSuccess;
+    }
+    if (ok && b->frontier) {
+      // after every class kernel (the join above): compact the frontier items
+      const char* base = (const char*)b->dev;
+      ok = spk::launch_batch_compact((const spk::CompactItem*)(base + b->off_compact),
+                                     (const int64_t*)(base + b->off_cprefix), (int)b->nets.size(), b->compact_blocks,
+                                     cs) == hipSuccess;
     }
     hipGraph_t g = nullptr;
     const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
@@ -307,6 +358,12 @@ spk_status spk_batch_create(spk_ctx* ctx, const spk_bound_opts* opts, int32_t n_
     p.off_nets = take(sizeof(spk::NetDev) * p.items.size());
     p.off_jobs = take(sizeof(spk::BoundJob) * p.items.size());
   }
+  for (int i = 0; i < n_items; ++i) b->frontier = b->frontier || items[i].cells != nullptr;
+  if (b->frontier) {
+    b->off_compact = take(sizeof(spk::CompactItem) * (size_t)n_items);
+    b->off_cprefix = take(sizeof(int64_t) * ((size_t)n_items + 1));
+    b->compact_blocks = ctx->num_cus * 8;
+  }
   b->off_counters = off;
   b->dev_bytes = off + sizeof(unsigned long long) * kCounterStride * b->classes.size();
   if (hipMalloc(&b->dev, b->dev_bytes) != hipSuccess) {
@@ -333,6 +390,7 @@ spk_status spk_batch_update(spk_ctx* ctx, spk_batch* b, int32_t n_items, const s
     if (items[i].net != b->nets[i]) return SPK_E_INVAL;
     spk_status st = valid_item(items[i]);
     if (st != SPK_OK) return st;
+    if (items[i].cells != nullptr && !b->frontier) return SPK_E_INVAL;   // the graph has no compaction
   }
   return write_descriptors(b, items, ctx->stream);
 }

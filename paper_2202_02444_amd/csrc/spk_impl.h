@@ -131,6 +131,20 @@ struct CpDive {
   float* point;              // [n][3] candidates
 };
 
+// One network's frontier round inside the batched graph (tree.hip).
+struct CompactItem {
+  const uint8_t* labels;
+  const uint64_t* cells;
+  int64_t n;                 // 0 for box items
+  int32_t at_max;
+  int32_t pad;
+  uint64_t* children;
+  int64_t cap_children;
+  uint64_t* leaves;
+  int64_t cap_leaves;
+  unsigned long long* counts;   // nullable (box items)
+};
+
 // Frustum ray casting (frustum.hip).
 struct Frustum {
   int32_t x0, x1, y0, y1;   // pixel rectangle [x0, x1) x [y0, y1)
@@ -229,6 +243,10 @@ spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, c
 spk_status launch_cp_init(int64_t n, uint64_t* codes, uint32_t* qidx, unsigned* best, float* point,
                           hipStream_t stream, int num_cus);
 spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t stream, int num_cus);
+// The batched graph's compaction: zero every item's counts, then compact the
+// labelled cells of every item (one launch each).
+hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix, int n_items, int blocks,
+                                hipStream_t stream);
 spk_status launch_fr_init(const FrRound& R, int tiles_x, int tiles_y, hipStream_t stream);
 spk_status launch_fr_box(const FrRound& R, int64_t m, hipStream_t stream);
 spk_status launch_fr_update(const FrRound& R, int64_t m, hipStream_t stream);

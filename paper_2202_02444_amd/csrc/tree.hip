@@ -11,6 +11,43 @@ __global__ void zero_counts_kernel(unsigned long long* counts) {
   if (threadIdx.x < 4) counts[threadIdx.x] = 0ull;
 }
 
+// One wave's chunk of 64 consecutive cells [base, base + 64) of a round.
+__device__ __forceinline__ void compact_chunk(const uint8_t* __restrict__ labels, const uint64_t* __restrict__ cells,
+                                              int64_t n, int at_max, uint64_t* __restrict__ children,
+                                              int64_t cap_children, uint64_t* __restrict__ leaves, int64_t cap_leaves,
+                                              unsigned long long* counts, int64_t base, int lane) {
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int64_t i = base + lane;
+  const bool in = i < n;
+  const uint8_t lab = in ? labels[i] : (uint8_t)255;
+  const bool unk = lab == SPK_UNKNOWN;
+  const unsigned long long mu = __ballot(unk);
+  const unsigned long long mp = __ballot(lab == SPK_POSITIVE);
+  const unsigned long long mn = __ballot(lab == SPK_NEGATIVE);
+  const int nu = __popcll(mu);
+  unsigned long long off = 0ull;
+  if (lane == 0) {
+    if (nu) off = atomicAdd(&counts[at_max ? 1 : 0], (unsigned long long)(at_max ? nu : 8 * nu));
+    if (mp) atomicAdd(&counts[2], (unsigned long long)__popcll(mp));
+    if (mn) atomicAdd(&counts[3], (unsigned long long)__popcll(mn));
+  }
+  off = __shfl(off, 0, 64);
+  if (unk) {
+    const int64_t pre = __popcll(mu & below);
+    const uint64_t code = cells[i];
+    if (at_max) {
+      const int64_t p = (int64_t)off + pre;
+      if (p < cap_leaves) leaves[p] = code;
+    } else {
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const int64_t p = (int64_t)off + 8 * pre + o;
+        if (p < cap_children) children[p] = (code << 3) | (uint64_t)o;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict__ labels,
                                                       const uint64_t* __restrict__ cells, int64_t n, int at_max,
                                                       uint64_t* __restrict__ children, int64_t cap_children,
@@ -18,38 +55,34 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict_
                                                       unsigned long long* counts) {
   const int lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
-    const int64_t i = base + lane;
-    const bool in = i < n;
-    const uint8_t lab = in ? labels[i] : (uint8_t)255;
-    const bool unk = lab == SPK_UNKNOWN;
-    const unsigned long long mu = __ballot(unk);
-    const unsigned long long mp = __ballot(lab == SPK_POSITIVE);
-    const unsigned long long mn = __ballot(lab == SPK_NEGATIVE);
-    const int nu = __popcll(mu);
-    unsigned long long off = 0ull;
-    if (lane == 0) {
-      if (nu) off = atomicAdd(&counts[at_max ? 1 : 0], (unsigned long long)(at_max ? nu : 8 * nu));
-      if (mp) atomicAdd(&counts[2], (unsigned long long)__popcll(mp));
-      if (mn) atomicAdd(&counts[3], (unsigned long long)__popcll(mn));
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride)
+    compact_chunk(labels, cells, n, at_max, children, cap_children, leaves, cap_leaves, counts, base, lane);
+}
+
+// The rounds of many networks at once (the batched graph): wave chunks are
+// numbered across the items by the prefix sums of their chunk counts.
+__global__ __launch_bounds__(256) void batch_compact_kernel(const CompactItem* items, const int64_t* prefix,
+                                                            int n_items) {
+  const int lane = threadIdx.x & 63;
+  const int64_t total = prefix[n_items];
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t cid = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); cid < total; cid += waves) {
+    int lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (prefix[mid] <= cid) lo = mid;
+      else hi = mid;
     }
-    off = __shfl(off, 0, 64);
-    if (unk) {
-      const int64_t pre = __popcll(mu & below);
-      const uint64_t code = cells[i];
-      if (at_max) {
-        const int64_t p = (int64_t)off + pre;
-        if (p < cap_leaves) leaves[p] = code;
-      } else {
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-          const int64_t p = (int64_t)off + 8 * pre + o;
-          if (p < cap_children) children[p] = (code << 3) | (uint64_t)o;
-        }
-      }
-    }
+    const CompactItem it = items[lo];
+    compact_chunk(it.labels, it.cells, it.n, it.at_max, it.children, it.cap_children, it.leaves, it.cap_leaves,
+                  it.counts, 64 * (cid - prefix[lo]), lane);
   }
+}
+
+__global__ void batch_counts_zero_kernel(const CompactItem* items, int n_items) {
+  for (int i = threadIdx.x; i < n_items; i += blockDim.x)
+    if (items[i].counts != nullptr)
+      for (int c = 0; c < 4; ++c) items[i].counts[c] = 0ull;
 }
 
 // Device status of a round (spk_device_status layout: nospc at byte 8, the
@@ -64,6 +97,15 @@ __global__ void round_status_kernel(const unsigned long long* counts, int64_t ca
     atomicMax((unsigned long long*)(status + 16), nc);
     atomicMax((unsigned long long*)(status + 24), nl);
   }
+}
+
+hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix, int n_items, int blocks,
+                                hipStream_t stream) {
+  hipLaunchKernelGGL(batch_counts_zero_kernel, dim3(1), dim3(256), 0, stream, items, n_items);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_compact_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, items, prefix, n_items);
+  return hipGetLastError();
 }
 
 spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t n, bool at_max, uint64_t* children,

@@ -31,9 +31,7 @@ EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy",
 
 
 class BatchItem(ctypes.Structure):
-    _fields_ = [("net", ctypes.c_void_p), ("n", ctypes.c_int64), ("box_lo", ctypes.c_void_p),
-                ("box_hi", ctypes.c_void_p), ("label", ctypes.c_void_p), ("lo", ctypes.c_void_p),
-                ("hi", ctypes.c_void_p)]
+    pass
 
 
 class BatchClass(ctypes.Structure):
@@ -88,6 +86,13 @@ class RayParams(ctypes.Structure):
                 ("eta_minus", ctypes.c_float), ("eta_plus", ctypes.c_float), ("safety", ctypes.c_float),
                 ("max_iters", ctypes.c_int32), ("clip_to_domain", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
+
+BatchItem._fields_ = [("net", ctypes.c_void_p), ("n", ctypes.c_int64), ("box_lo", ctypes.c_void_p),
+                      ("box_hi", ctypes.c_void_p), ("label", ctypes.c_void_p), ("lo", ctypes.c_void_p),
+                      ("hi", ctypes.c_void_p), ("cells", ctypes.c_void_p), ("level", ctypes.c_int32),
+                      ("reserved", ctypes.c_int32), ("tree", TreeParams), ("children", ctypes.c_void_p),
+                      ("cap_children", ctypes.c_int64), ("leaves", ctypes.c_void_p), ("cap_leaves", ctypes.c_int64),
+                      ("counts", ctypes.c_void_p)]
 
 Request._fields_ = [("type", ctypes.c_int32), ("net", ctypes.c_int32), ("n", ctypes.c_int64),
                     ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("out0", ctypes.c_void_p),
@@ -394,17 +399,40 @@ class Batch:
         self.handle = h
 
     def _items(self, items):
+        """Box items: box_lo, box_hi, label (lo, hi optional).  Frontier items:
+        cells ([n] int64 Morton codes), level, label, counts ([4] int64),
+        children / leaves (capacity = their length; optional), max_level,
+        dom_lo, dom_hi."""
         import torch
         arr = (BatchItem * len(items))()
+
+        def v(p):
+            return None if p is None else p.value
         for i, it in enumerate(items):
-            n = it["box_lo"].shape[0]
-            def v(p):
-                return None if p is None else p.value
-            arr[i] = BatchItem(it["net"].handle.value, n, v(_ptr(it["box_lo"], torch.float32, (n, 3), "box_lo")),
-                               v(_ptr(it["box_hi"], torch.float32, (n, 3), "box_hi")),
-                               v(_ptr(it["label"], torch.uint8, (n,), "label")),
-                               v(_ptr(it.get("lo"), torch.float32, (n,), "lo")),
-                               v(_ptr(it.get("hi"), torch.float32, (n,), "hi")))
+            b = BatchItem()
+            b.net = it["net"].handle.value
+            if it.get("cells") is not None:
+                n = it["cells"].shape[0]
+                b.n = n
+                b.cells = v(_ptr(it["cells"], torch.int64, (n,), "cells"))
+                b.level = int(it["level"])
+                b.tree = TreeParams((ctypes.c_float * 3)(*it.get("dom_lo", (-1.0,) * 3)),
+                                    (ctypes.c_float * 3)(*it.get("dom_hi", (1.0,) * 3)), int(it["max_level"]), 8)
+                ch, lv = it.get("children"), it.get("leaves")
+                b.children = v(_ptr(ch, torch.int64, None, "children")) if ch is not None and ch.numel() else None
+                b.cap_children = int(ch.numel()) if ch is not None else 0
+                b.leaves = v(_ptr(lv, torch.int64, None, "leaves")) if lv is not None and lv.numel() else None
+                b.cap_leaves = int(lv.numel()) if lv is not None else 0
+                b.counts = v(_ptr(it["counts"], torch.int64, (4,), "counts"))
+            else:
+                n = it["box_lo"].shape[0]
+                b.n = n
+                b.box_lo = v(_ptr(it["box_lo"], torch.float32, (n, 3), "box_lo"))
+                b.box_hi = v(_ptr(it["box_hi"], torch.float32, (n, 3), "box_hi"))
+            b.label = v(_ptr(it["label"], torch.uint8, (n,), "label"))
+            b.lo = v(_ptr(it.get("lo"), torch.float32, (n,), "lo"))
+            b.hi = v(_ptr(it.get("hi"), torch.float32, (n,), "hi"))
+            arr[i] = b
         self._keep = list(items)   # the device buffers must outlive their use
         return arr
 
@@ -529,6 +557,55 @@ def eval_points(ctx, net, x, f):
     st = lib().spk_eval_points(ctx.handle, net.handle, n, _ptr(x, torch.float32, (n, 3), "x"),
                                _ptr(f, torch.float32, (n,), "f"))
     _check(st, "spk_eval_points")
+
+
+def build_octrees_batched(ctx, nets, max_level, policy="truncate", k=31, rigorous=True, tune=False,
+                          dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3):
+    """Fixed-depth octrees of many networks at once: every level is one
+    batched graph launch that classifies every network's frontier cells and
+    compacts every frontier (spk_batch_* with frontier items).  Returns per
+    network the per-level stats and the UNKNOWN leaf cells at max_level."""
+    import torch
+    dev = torch.device("cuda")
+    m = len(nets)
+    counts = torch.zeros((m, 4), dtype=torch.int64, device=dev)
+    cells = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(m)]
+    levels = [[] for _ in range(m)]
+    leaves = [torch.zeros(0, dtype=torch.int64, device=dev) for _ in range(m)]
+
+    def items_for(level):
+        at_max = level == max_level
+        out = []
+        for i in range(m):
+            n = cells[i].shape[0]
+            out.append({"net": nets[i], "cells": cells[i], "level": level, "max_level": max_level,
+                        "dom_lo": dom_lo, "dom_hi": dom_hi, "label": torch.empty(n, dtype=torch.uint8, device=dev),
+                        "counts": counts[i],
+                        "children": None if at_max else torch.empty(8 * n, dtype=torch.int64, device=dev),
+                        "leaves": torch.empty(n, dtype=torch.int64, device=dev) if at_max else None})
+        return out
+    its = items_for(0)
+    b = Batch(ctx, its, policy, k, rigorous)
+    try:
+        for level in range(max_level + 1):
+            if level > 0:
+                its = items_for(level)
+                b.update(ctx, its)
+            if tune and level == max_level // 2:
+                b.tune(ctx, reps=1)
+            b.launch(ctx)
+            ctx.sync()
+            c = counts.cpu().tolist()
+            for i in range(m):
+                levels[i].append({"level": level, "n": int(cells[i].shape[0]), "n_children": c[i][0],
+                                  "n_leaves": c[i][1], "n_pos": c[i][2], "n_neg": c[i][3]})
+                if level == max_level:
+                    leaves[i] = its[i]["leaves"][:c[i][1]]
+                else:
+                    cells[i] = its[i]["children"][:c[i][0]]
+    finally:
+        b.close()
+    return levels, leaves
 
 
 def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3,

@@ -194,6 +194,28 @@ def test_batch_validation():
     assert L.spk_batch_destroy(None) == spk.E_INVAL
     n = ctypes.c_int32()
     assert L.spk_batch_classes(None, ctypes.byref(n), None, 0) == spk.E_INVAL
+    # frontier items are checked before any device access
+    f = spk.BatchItem()
+    f.net, f.n, f.cells, f.label, f.counts, f.level = 0x1000, 4, 0x1000, 0x1000, 0x1000, 1
+    f.tree = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 3, 2)
+    items[0] = f
+    assert L.spk_batch_create(FAKE, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_UNSUPPORTED   # k-d
+    f.tree.arity = 8
+    f.level = 4                                                       # beyond max_level
+    items[0] = f
+    assert L.spk_batch_create(FAKE, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_INVAL
+    f.level = 1
+    f.counts = None
+    items[0] = f
+    assert L.spk_batch_create(FAKE, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_INVAL   # no counts
+    f.counts = 0x1000
+    f.cap_children = 8                                                # capacity without a buffer
+    items[0] = f
+    assert L.spk_batch_create(FAKE, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_INVAL
+    f.cap_children = 0
+    f.tree.dom_hi[0] = -2.0                                           # empty domain
+    items[0] = f
+    assert L.spk_batch_create(FAKE, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_INVAL
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -171,3 +171,62 @@ def test_net_destroy_busy_while_held(ctx):
     gnets[0].close()                             # now frees
     assert gnets[0].handle is None
     gnets[1].close()
+
+
+@pytest.mark.parametrize("rigorous", [False, True])
+def test_batched_octrees_equal_single_network_octrees(ctx, rigorous):
+    """Frontier items: one graph launch per level classifies and compacts
+    every network's frontier.  Per network and level the counts, and the
+    final leaves, equal those of the single-network rounds
+    (spk_subdivide_frontier), bit for bit."""
+    from paper_2202_02444_amd import spk
+    specs = [wl.tiny_net(0), wl.he_normal_mlp([3, 64, 64, 64, 1], 51, act="elu", bias=-0.3),
+             wl.siren_mlp([3, 128, 128, 1], 52, 30.0), wl.scale_net(1), wl.tiny_net(7),
+             wl.he_normal_mlp([3, 64, 64, 1], 54, act="relu")]
+    gnets = [spk.Net.from_spec(s_) for s_ in specs]
+    depth = 5
+    levels_b, leaves_b = spk.build_octrees_batched(ctx, gnets, depth, "truncate", 31, rigorous=rigorous)
+    for i, g in enumerate(gnets):
+        levels_s, leaves_s = spk.build_octree(ctx, g, depth, "truncate", 31, rigorous=rigorous)
+        for a, b in zip(levels_b[i], levels_s):
+            assert a == b, (i, a, b)
+        la = np.sort(leaves_b[i].cpu().numpy())
+        lb = np.sort(leaves_s.cpu().numpy())
+        assert np.array_equal(la, lb), i
+    for g in gnets:
+        g.close()
+
+
+def test_batch_mixes_box_and_frontier_items(ctx):
+    """Box items and frontier items in one batch: the boxes get the labels of
+    a single classify launch, the frontier item the counts and children of a
+    single subdivide round; a frontier that outgrows its capacity reports the
+    required size and writes only its capacity."""
+    import torch
+    from paper_2202_02444_amd import spk
+    specs = [wl.tiny_net(0), wl.he_normal_mlp([3, 64, 64, 1], 54, act="relu")]
+    gnets = [spk.Net.from_spec(s_) for s_ in specs]
+    box_items = _items(specs[:1], gnets[:1], [700], 91)
+    dev = torch.device("cuda")
+    cells = torch.arange(64, dtype=torch.int64, device=dev)            # all level-2 cells
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    small = torch.full((16,), -1, dtype=torch.int64, device=dev)
+    fr = {"net": gnets[1], "cells": cells, "level": 2, "max_level": 6, "label": torch.empty(64, dtype=torch.uint8,
+          device=dev), "counts": counts, "children": small}
+    b = spk.Batch(ctx, box_items + [fr], "truncate", 31)
+    b.launch(ctx)
+    ctx.sync()
+    lab, _, _ = _single(ctx, box_items[0], "truncate", 31)
+    np.testing.assert_array_equal(box_items[0]["label"].cpu().numpy(), lab)
+    ref_counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    big = torch.empty(8 * 64, dtype=torch.int64, device=dev)
+    spk.subdivide_frontier(ctx, gnets[1], 2, cells, big, None, ref_counts, 6, "truncate", 31)
+    ctx.sync(allow_nospc=True)
+    c, rc = counts.cpu().numpy(), ref_counts.cpu().numpy()
+    np.testing.assert_array_equal(c, rc)
+    assert c[0] > 16 and np.all(small.cpu().numpy() >= 0)
+    want = np.sort(big[:rc[0]].cpu().numpy())
+    assert np.all(np.isin(small.cpu().numpy(), want))
+    b.close()
+    for g in gnets:
+        g.close()
