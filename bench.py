@@ -197,10 +197,26 @@ def batched_extra(ctx, dev, policy="truncate", k=K_KEEP):
     seq_ms = ev[1].elapsed_time(ev[2])
     classes = b.classes()
     b.close()
+    # octrees of all 64 networks to depth 5: one graph launch per level
+    # (frontier items) against the single-network rounds, after a warm-up
+    gn = [it["net"] for it in items]
+    spk.build_octrees_batched(ctx, gn, 2, policy, k)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lv_b, _ = spk.build_octrees_batched(ctx, gn, 5, policy, k)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    t = time.perf_counter()
+    lv_s = [spk.build_octree(ctx, g_, 5, policy, k)[0] for g_ in gn]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    same = all(a == b_ for x, y in zip(lv_b, lv_s) for a, b_ in zip(x, y))
     return {"nets": len(nets), "boxes": total, "graph_boxes_per_s": total / (graph_ms * 1e-3),
             "sequential_boxes_per_s": total / (seq_ms * 1e-3), "graph_ms": graph_ms, "sequential_ms": seq_ms,
             "classes": [{"width": c["width"], "act": c["act"], "nets": c["n_nets"], "blocks": c["blocks"],
-                         "chunk": c["chunk"]} for c in classes]}
+                         "chunk": c["chunk"]} for c in classes],
+            "octrees_depth5": {"cells": int(sum(l_["n"] for lv in lv_b for l_ in lv)), "batched_s": tb,
+                               "sequential_s": ts, "speedup": ts / tb, "identical": bool(same)}}
 
 
 def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, steps=2):

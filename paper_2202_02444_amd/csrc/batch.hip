@@ -303,10 +303,12 @@ spk_status capture(spk_batch* b) {
   return st;
 }
 
+// Four persistent workgroups per CU, whatever the class's work at capture
+// time: updates may grow the frontiers (a wave that finds the queue empty
+// exits at once).
 int default_blocks(const spk_batch* b, const ClassPlan& p) {
-  int64_t blocks = (int64_t)b->num_cus * 4;
-  if (blocks > p.groups) blocks = p.groups;
-  return (int)std::max<int64_t>(blocks, 1);
+  (void)p;
+  return std::max(b->num_cus * 4, 1);
 }
 
 }  // namespace
@@ -419,7 +421,7 @@ spk_status spk_batch_tune(spk_ctx* ctx, spk_batch* b, int32_t reps) {
     int best_blocks = p.blocks, best_chunk = p.chunk;
     for (int pc : per_cu) {
       for (int ck : chunks) {
-        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)b->num_cus * pc, p.groups));
+        const int blocks = std::max(1, b->num_cus * pc);   // not capped by the current work: it may grow
         p.chunk = ck;
         BatchArgs a = class_args(b, (int)c);
         float total = 0.0f;
