@@ -275,6 +275,19 @@ typedef struct {
 } spk_ray_params;
 
 /*
+ * spk_empty_spheres (Section 4.4): for each point p_i (dev [n][3]) the first
+ * radius r in r0, r0/2, r0/4, ... with r >= r_min such that the bound
+ * classifies the cube [p - r, p + r]^3 (rounded outwards) as POSITIVE or
+ * NEGATIVE, so that the ball of radius r around p holds no point of the level
+ * set.  radius dev [n]: that r, 0 if none; label dev uint8 [n]: the cube's
+ * class (UNKNOWN with radius 0).  Synchronous (one host round trip per
+ * halving); buffers about 45 bytes per point, stream-ordered within the
+ * context's workspace limit.  0 < r_min <= r0 (finite), else SPK_E_INVAL.
+ */
+spk_status spk_empty_spheres(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n, const float* p,
+                             float r0, float r_min, float* radius, uint8_t* label);
+
+/*
  * Frustum ray casting (Section 4.3; Appendix B).  A pinhole camera: pixel
  * (px, py), row-major from the top row, looks from eye along
  * normalize(forward + x right + y up) with

@@ -8,6 +8,7 @@
 * :func:`closest_point` -- Section 4.10 lazy best-first descent.
 * :func:`cast_frusta`   -- Section 4.3 frustum ray casting (Appendix B split
   rule and spherical-front box), ending in Procedure 2 per pixel.
+* :func:`empty_spheres` -- Section 4.4 empty-sphere radii by shrinking cubes.
 """
 from __future__ import annotations
 
@@ -461,3 +462,33 @@ def cast_frusta(net, cam, tiles=(16, 16), delta=1e-3, sigma0=1.0, eta_minus=0.5,
         t_hit[pix] = th + rel
         steps[pix] += it
     return t_hit, steps
+
+
+# ---------------------------------------------------------------------------
+# Empty spheres (Section 4.4)
+# ---------------------------------------------------------------------------
+
+def empty_spheres(net, p, r0=1.0, r_min=1e-4, policy="truncate", k=31):
+    """For each point the first radius r in r0, r0/2, r0/4, ... (not below
+    r_min) such that RangeBound classifies the cube [p - r, p + r]^3 as
+    POSITIVE or NEGATIVE: the ball of radius r around p (inside that cube)
+    then holds no point of the level set.  Returns (radius [n], 0 where no
+    such r; label [n], UNKNOWN where radius is 0)."""
+    p = np.asarray(p, dtype=np.float64)
+    n = p.shape[0]
+    radius = np.zeros(n)
+    label = np.full(n, UNKNOWN, dtype=np.uint8)
+    r = np.full(n, float(r0))
+    act = np.arange(n)
+    while act.size:
+        lo = p[act] - r[act, None]
+        hi = p[act] + r[act, None]
+        _, _, ly, hy = mlp.bound_boxes(net, lo, hi, policy, k)
+        lab = classify(ly, hy)
+        done = lab != UNKNOWN
+        radius[act[done]] = r[act[done]]
+        label[act[done]] = lab[done]
+        rest = act[~done]
+        r[rest] = r[rest] * 0.5
+        act = rest[r[rest] >= r_min]
+    return radius, label

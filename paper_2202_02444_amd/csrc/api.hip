@@ -862,6 +862,86 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
   return check_hip(hipStreamSynchronize(ctx->stream));
 }
 
+// Empty spheres (Section 4.4); kernels in spheres.hip.
+spk_status spk_empty_spheres(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n, const float* p,
+                             float r0, float r_min, float* radius, uint8_t* label) {
+  if (ctx == nullptr || net == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
+  if (st != SPK_OK) return st;
+  if (n < 0 || !(r0 > 0.0f) || !(r_min > 0.0f) || !(r_min <= r0) || !isfinite(r0)) return SPK_E_INVAL;
+  if (n == 0) return SPK_OK;
+  if (p == nullptr || radius == nullptr || label == nullptr) return SPK_E_INVAL;
+  void *cur = nullptr, *rc = nullptr, *lc = nullptr, *nx = nullptr, *rn = nullptr, *cnt = nullptr, *blo = nullptr,
+       *bhi = nullptr;
+  size_t c_cur = 0, c_rc = 0, c_lc = 0, c_nx = 0, c_rn = 0, c_cnt = 0, c_blo = 0, c_bhi = 0;
+  CallBuffers B;
+  B.limit = ctx->workspace_limit;
+  B.stream = ctx->stream;
+  B.peak = &ctx->ws_peak;
+#define SPK_ES_ENSURE(ptr, cap, bytes)              \
+  do {                                              \
+    spk_status e_ = B.ensure(&(ptr), cap, (bytes)); \
+    if (e_ != SPK_OK) return e_;                    \
+  } while (0)
+  SPK_ES_ENSURE(cur, c_cur, (size_t)n * 8);
+  SPK_ES_ENSURE(rc, c_rc, (size_t)n * 4);
+  SPK_ES_ENSURE(lc, c_lc, (size_t)n);
+  SPK_ES_ENSURE(nx, c_nx, (size_t)n * 8);
+  SPK_ES_ENSURE(rn, c_rn, (size_t)n * 4);
+  SPK_ES_ENSURE(cnt, c_cnt, 256);
+  SPK_ES_ENSURE(blo, c_blo, (size_t)n * 12);
+  SPK_ES_ENSURE(bhi, c_bhi, (size_t)n * 12);
+#undef SPK_ES_ENSURE
+  EsRound E = {};
+  E.n = n;
+  E.p = p;
+  E.r0 = r0;
+  E.r_min = r_min;
+  E.cur = (int64_t*)cur;
+  E.r_cur = (float*)rc;
+  E.lab_cur = (const uint8_t*)lc;
+  E.next = (int64_t*)nx;
+  E.r_next = (float*)rn;
+  E.count = (unsigned long long*)cnt;
+  E.box_lo = (float*)blo;
+  E.box_hi = (float*)bhi;
+  E.radius = radius;
+  E.label = label;
+  st = launch_es_init(E, ctx->stream);
+  if (st != SPK_OK) return st;
+  int64_t m = n;
+  for (int round = 0; m > 0; ++round) {
+    if (round > 200) return SPK_E_DEVICE;   // not reached: r halves each round down to r_min
+    st = launch_es_boxes(E, m, ctx->stream);
+    if (st != SPK_OK) return st;
+    BoundJob job = {};
+    job.n = m;
+    job.mode = IN_AABB;
+    job.s = 3;
+    job.policy = opts->policy;
+    job.k = opts->k;
+    job.prec = opts->prec;
+    job.rigorous = rigorous_opts(opts) ? 1 : 0;
+    job.a = E.box_lo;
+    job.b = E.box_hi;
+    job.label = (uint8_t*)lc;
+    job.nonfinite = (unsigned long long*)ctx->status;
+    st = launch_bound(net, job, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+    st = launch_es_update(E, m, ctx->stream);
+    if (st != SPK_OK) return st;
+    unsigned long long next = 0ull;
+    if (hipMemcpyAsync(&next, cnt, sizeof(next), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return SPK_E_DEVICE;
+    m = (int64_t)next;
+    if (m > n) return SPK_E_DEVICE;
+    std::swap(E.cur, E.next);
+    std::swap(E.r_cur, E.r_next);
+  }
+  return check_hip(hipStreamSynchronize(ctx->stream));
+}
+
 // Frustum ray casting (Section 4.3; Appendix B); kernels in frustum.hip.
 spk_status spk_cast_frusta(spk_ctx* ctx, const spk_net* net, const spk_ray_params* params,
                            const spk_bound_opts* box_opts, const spk_camera* cam, int32_t tiles_x, int32_t tiles_y,

@@ -131,6 +131,23 @@ struct CpDive {
   float* point;              // [n][3] candidates
 };
 
+// Empty-sphere rounds (spheres.hip).
+struct EsRound {
+  int64_t n;
+  const float* p;            // [n][3] query points
+  float r0, r_min;
+  int64_t* cur;              // [m] live queries of the round
+  float* r_cur;              // [m] their radii
+  const uint8_t* lab_cur;    // [m] labels of their cubes
+  int64_t* next;             // [n] next round
+  float* r_next;
+  unsigned long long* count;   // next round's size
+  float* box_lo;             // [m][3]
+  float* box_hi;
+  float* radius;             // [n] outputs
+  uint8_t* label;
+};
+
 // One network's frontier round inside the batched graph (tree.hip).
 struct CompactItem {
   const uint8_t* labels;
@@ -247,6 +264,9 @@ spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t str
 // labelled cells of every item (one launch each).
 hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix, int n_items, int blocks,
                                 hipStream_t stream);
+spk_status launch_es_init(const EsRound& E, hipStream_t stream);
+spk_status launch_es_boxes(const EsRound& E, int64_t m, hipStream_t stream);
+spk_status launch_es_update(const EsRound& E, int64_t m, hipStream_t stream);
 spk_status launch_fr_init(const FrRound& R, int tiles_x, int tiles_y, hipStream_t stream);
 spk_status launch_fr_box(const FrRound& R, int64_t m, hipStream_t stream);
 spk_status launch_fr_update(const FrRound& R, int64_t m, hipStream_t stream);

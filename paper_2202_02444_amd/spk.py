@@ -24,6 +24,7 @@ UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
            "spk_subdivide_frontier", "spk_subdivide_frontier_noalloc", "spk_cast_rays", "spk_cast_frusta",
+           "spk_empty_spheres",
            "spk_eval_points", "spk_closest_point",
            "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
            "spk_batch_destroy", "spk_server_create", "spk_server_submit", "spk_server_poll",
@@ -131,6 +132,8 @@ def lib():
         L.spk_subdivide_frontier_noalloc.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
+        L.spk_empty_spheres.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, vp, ctypes.c_float,
+                                        ctypes.c_float, vp, vp]
         L.spk_cast_frusta.argtypes = [vp, vp, ctypes.POINTER(RayParams), ctypes.POINTER(BoundOpts),
                                       ctypes.POINTER(Camera), i32, i32, vp, vp, ctypes.POINTER(FrustumStats)]
         L.spk_eval_points.argtypes = [vp, vp, i64, vp, vp]
@@ -340,6 +343,18 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
                              _ptr(direction, torch.float32, (n, 3), "direction"),
                              _ptr(t_hit, torch.float32, (n,), "t_hit"), _ptr(iters, torch.int32, (n,), "iters"))
     _check(st, "spk_cast_rays")
+
+
+def empty_spheres(ctx, net, p, radius, label, r0=1.0, r_min=1e-4, policy="truncate", k=31, rigorous=True,
+                  prec="f32"):
+    """spk_empty_spheres: radius [n] and label [n] for the points p [n, 3]."""
+    import torch
+    n = p.shape[0]
+    o = opts(policy, k, rigorous, prec)
+    st = lib().spk_empty_spheres(ctx.handle, net.handle, ctypes.byref(o), n, _ptr(p, torch.float32, (n, 3), "p"),
+                                 float(r0), float(r_min), _ptr(radius, torch.float32, (n,), "radius"),
+                                 _ptr(label, torch.uint8, (n,), "label"))
+    _check(st, "spk_empty_spheres")
 
 
 def camera(cam):

@@ -131,6 +131,21 @@ def test_tree_and_ray_validation():
     assert spk.ray_params(rigorous=False).flags == spk.FLAG_NO_ROUNDING_BOUND and spk.ray_params().flags == 0
 
 
+def test_empty_spheres_validation():
+    L = spk.lib()
+    o = spk.opts("truncate", 31)
+    f = ctypes.c_float
+    assert L.spk_empty_spheres(None, FAKE, ctypes.byref(o), 4, FAKE, f(1.0), f(1e-3), FAKE, FAKE) == spk.E_INVAL
+    assert L.spk_empty_spheres(FAKE, FAKE, ctypes.byref(o), 4, FAKE, f(1e-3), f(1.0), FAKE, FAKE) == spk.E_INVAL
+    assert L.spk_empty_spheres(FAKE, FAKE, ctypes.byref(o), 4, FAKE, f(0.0), f(0.0), FAKE, FAKE) == spk.E_INVAL
+    assert L.spk_empty_spheres(FAKE, FAKE, ctypes.byref(o), 4, FAKE, f(1.0), f(1e-3), None, FAKE) == spk.E_INVAL
+    assert L.spk_empty_spheres(FAKE, FAKE, ctypes.byref(o), -1, FAKE, f(1.0), f(1e-3), FAKE, FAKE) == spk.E_INVAL
+    assert L.spk_empty_spheres(FAKE, FAKE, ctypes.byref(o), 0, None, f(1.0), f(1e-3), None, None) == spk.OK
+    bad = spk.opts("truncate", 40)
+    assert L.spk_empty_spheres(FAKE, FAKE, ctypes.byref(bad), 4, FAKE, f(1.0), f(1e-3), FAKE,
+                               FAKE) == spk.E_UNSUPPORTED
+
+
 def test_frustum_validation():
     L = spk.lib()
     cam = spk.camera(wl.camera(8, 6, 1))

@@ -408,3 +408,57 @@ def test_closest_point_chunk_halving(ctx):
     finally:
         tiny.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("rigorous", [False, True])
+@pytest.mark.parametrize("netname", ["tiny", "blob", "sin64"])
+def test_empty_spheres_vs_oracle(ctx, netname, rigorous):
+    """Section 4.4: the GPU radii against the oracle's.  In the paper's
+    arithmetic they are equal unless a tried cube's oracle bound lies within
+    the parity tolerance of zero; in the rounding-bounded mode the GPU radius
+    is never larger than the oracle's (its bounds contain the exact ones).
+    Every returned cube holds no sign change of f (corners, center and random
+    points evaluated in FP64) and has the reported sign."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = {"tiny": wl.tiny_net(0), "blob": wl.scale_net(1),
+           "sin64": wl.siren_mlp([3, 64, 64, 1], 45, omega0=30.0)}[netname]
+    g = spk.Net.from_spec(net)
+    n = 700 if netname != "blob" else 300
+    pts = wl.points(n, 31)
+    pts[0] = np.nan                                      # a non-finite point: radius 0
+    dev = torch.device("cuda")
+    rad = torch.empty(n, device=dev)
+    lab = torch.empty(n, dtype=torch.uint8, device=dev)
+    r0, rmin = 0.5, 1.0 / 4096
+    ctx.sync()
+    spk.empty_spheres(ctx, g, torch.from_numpy(pts).to(dev), rad, lab, r0, rmin, rigorous=rigorous)
+    st = ctx.sync()
+    assert st["nonfinite_inputs"] >= 1
+    rg, lg = rad.cpu().numpy().astype(np.float64), lab.cpu().numpy()
+    assert rg[0] == 0.0 and lg[0] == spk.UNKNOWN
+    ro, lo_ = oq.empty_spheres(net, pts[1:].astype(np.float64), r0, rmin)
+    rg, lg = rg[1:], lg[1:]
+    assert np.all((rg == 0) == (lg == spk.UNKNOWN))
+    S = s_net(net)
+    if rigorous:
+        assert np.all(rg <= ro), np.flatnonzero(rg > ro)[:5]
+    else:
+        differ = np.flatnonzero(rg != ro)
+        # a differing radius must come from a cube whose oracle bound is within
+        # the tolerance of zero: re-bound the larger of the two cubes
+        if differ.size:
+            r = np.maximum(rg[differ], ro[differ])
+            p_ = pts[1:][differ].astype(np.float64)
+            _, _, ly, hy = omlp.bound_boxes(net, p_ - r[:, None], p_ + r[:, None], "truncate", 31)
+            assert np.all(label_ambiguous(ly, hy, S, 4e-6 * (np.abs(ly) + np.abs(hy)))), differ[:5]
+        assert differ.size <= max(2, rg.size // 50)
+    # soundness of every returned cube
+    ok = np.flatnonzero(rg > 0)
+    rng = np.random.default_rng(8)
+    p_ = pts[1:][ok].astype(np.float64)
+    from parity import sample_points
+    P = sample_points(p_ - rg[ok, None], p_ + rg[ok, None], rng, 6)
+    f = omlp.forward(net, P.reshape(-1, 3)).reshape(ok.size, -1)
+    pos = lg[ok] == spk.POSITIVE
+    assert np.all(f[pos] > 0) and np.all(f[~pos] < 0)

@@ -316,3 +316,37 @@ def test_frustum_cast_matches_ray_cast(netname):
     dirs = q.pixel_dirs(cam, np.arange(576) % 24, np.arange(576) // 24)
     bad = ray_contract_violations(net, np.broadcast_to(cam["eye"], (576, 3)), dirs, th, differ, delta, 1e-9)
     assert not bad, bad[:5]
+
+
+def _l1_range_over_box(lo, hi):
+    """Exact range of |x|_1 over an axis-aligned box."""
+    mx = np.maximum(np.abs(lo), np.abs(hi)).sum(axis=1)
+    mn = np.where((lo <= 0) & (hi >= 0), 0.0, np.minimum(np.abs(lo), np.abs(hi))).sum(axis=1)
+    return mn, mx
+
+
+def test_empty_spheres_octahedron_closed_form():
+    """On the exact octahedron |x|_1 = R: every returned cube lies strictly on
+    one side of the surface (closed-form range of |x|_1), with the right sign;
+    a point on the surface gets radius 0; radii are r0 / 2^j; the center,
+    0.6 from the surface in |x|_1, gets a NEGATIVE cube of half-width at least
+    0.125 (whose |x|_1 stays below 0.375)."""
+    R = 0.6
+    net = wl.octahedron_mlp(R)
+    rng = np.random.default_rng(3)
+    p = rng.uniform(-1, 1, (300, 3))
+    p[0] = [R, 0.0, 0.0]                       # on the surface
+    p[1] = [0.0, 0.0, 0.0]                     # the center, 0.6 from the surface
+    r0, rmin = 0.5, 1e-3
+    rad, lab = q.empty_spheres(net, p, r0, rmin)
+    assert rad[0] == 0.0 and lab[0] == q.UNKNOWN
+    ok = rad > 0
+    j = np.log2(r0 / rad[ok])
+    assert np.allclose(j, np.round(j))
+    lo, hi = p[ok] - rad[ok, None], p[ok] + rad[ok, None]
+    mn, mx = _l1_range_over_box(lo, hi)
+    pos = lab[ok] == q.POSITIVE
+    assert np.all(mn[pos] > R) and np.all(mx[~pos] < R)
+    # the center: the cube of half-width 0.5 has |x|_1 <= 1.5 > R, so it is not
+    # classified; 0.125 (|x|_1 <= 0.375) must be
+    assert lab[1] == q.NEGATIVE and rad[1] >= 0.125
