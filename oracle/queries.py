@@ -9,6 +9,8 @@
 * :func:`cast_frusta`   -- Section 4.3 frustum ray casting (Appendix B split
   rule and spherical-front box), ending in Procedure 2 per pixel.
 * :func:`empty_spheres` -- Section 4.4 empty-sphere radii by shrinking cubes.
+* :func:`intersect`     -- Section 4.9 intersection test of two shapes on a
+  shared octree.
 """
 from __future__ import annotations
 
@@ -492,3 +494,45 @@ def empty_spheres(net, p, r0=1.0, r_min=1e-4, policy="truncate", k=31):
         r[rest] = r[rest] * 0.5
         act = rest[r[rest] >= r_min]
     return radius, label
+
+
+# ---------------------------------------------------------------------------
+# Intersection of two implicit shapes (Section 4.9)
+# ---------------------------------------------------------------------------
+
+NO_INTERSECTION, INTERSECTION, UNDECIDED = 0, 1, 2
+
+
+def intersect(net_f, net_g, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1)):
+    """Test whether the solids {f < 0} and {g < 0} overlap, subdividing an
+    octree with respect to both functions in parallel rounds: a cell where
+    either function is bounded POSITIVE cannot hold a common point and is
+    dropped; a cell where both are bounded NEGATIVE lies inside both solids
+    (an intersection; the round stops there, the witness is the smallest
+    Morton code of such cells at that level); other cells split until
+    max_level, where they remain undecided.
+
+    Returns a dict: result (NO_INTERSECTION, INTERSECTION, UNDECIDED), level
+    and cell of the witness, undecided (cells left at max_level) and the
+    per-level frontier sizes."""
+    codes = np.zeros(1, dtype=np.uint64)
+    sizes = []
+    for level in range(max_level + 1):
+        sizes.append(int(codes.size))
+        if codes.size == 0:
+            return {"result": NO_INTERSECTION, "level": -1, "cell": 0, "undecided": 0, "sizes": sizes}
+        lo, hi = cell_bounds(codes, level, dom_lo, dom_hi)
+        _, _, lf, hf = mlp.bound_boxes(net_f, lo, hi, policy, k)
+        _, _, lg, hg = mlp.bound_boxes(net_g, lo, hi, policy, k)
+        a, b = classify(lf, hf), classify(lg, hg)
+        both = (a == NEGATIVE) & (b == NEGATIVE)
+        if np.any(both):
+            return {"result": INTERSECTION, "level": level, "cell": int(codes[both].min()), "undecided": 0,
+                    "sizes": sizes}
+        keep = codes[(a != POSITIVE) & (b != POSITIVE)]
+        if level == max_level:
+            res = UNDECIDED if keep.size else NO_INTERSECTION
+            return {"result": res, "level": -1, "cell": 0, "undecided": int(keep.size), "sizes": sizes}
+        codes = np.sort(np.concatenate([(keep << np.uint64(3)) | np.uint64(o) for o in range(8)])) \
+            if keep.size else np.zeros(0, dtype=np.uint64)
+    raise AssertionError("unreachable")

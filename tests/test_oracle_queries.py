@@ -350,3 +350,36 @@ def test_empty_spheres_octahedron_closed_form():
     # the center: the cube of half-width 0.5 has |x|_1 <= 1.5 > R, so it is not
     # classified; 0.125 (|x|_1 <= 0.375) must be
     assert lab[1] == q.NEGATIVE and rad[1] >= 0.125
+
+
+def _octa_at(a, R):
+    """Exact ReLU network of |x - a|_1 - R (an octahedron centered at a)."""
+    a = np.asarray(a, dtype=np.float32)
+    W1 = np.concatenate([np.eye(3), -np.eye(3)]).astype(np.float32)
+    b1 = np.concatenate([-a, a]).astype(np.float32)
+    return wl.MLPSpec([W1, np.ones((1, 6), np.float32)], [b1, np.array([-R], np.float32)], act="relu")
+
+
+def test_intersect_octahedra_closed_form():
+    """Two L1 balls overlap iff the L1 distance of their centers is below the
+    sum of their radii.  Overlapping pairs give INTERSECTION with a witness
+    cell inside both (closed-form range of |x - a|_1 over the cell); a pair
+    with a clear gap gives NO_INTERSECTION; touching pairs are UNDECIDED at a
+    limited depth."""
+    R = 0.35
+    for shift, want in ((0.5, q.INTERSECTION), (0.9, q.NO_INTERSECTION), (0.7, None)):
+        f = _octa_at([-shift / 2, 0.0, 0.0], R)
+        g = _octa_at([shift / 2, 0.0, 0.0], R)
+        res = q.intersect(f, g, 6)
+        if want is not None:
+            assert res["result"] == want, (shift, res)
+        else:
+            assert res["result"] == q.UNDECIDED and res["undecided"] > 0
+        if res["result"] == q.INTERSECTION:
+            lo, hi = q.cell_bounds(np.array([res["cell"]], dtype=np.uint64), res["level"], (-1,) * 3, (1,) * 3)
+            for c in ([-shift / 2, 0, 0], [shift / 2, 0, 0]):
+                _, mx = _l1_range_over_box(lo - np.array(c), hi - np.array(c))
+                assert mx[0] < R
+    # a shape against itself: inside both wherever it is inside
+    f = _octa_at([0.1, 0.0, 0.0], 0.5)
+    assert q.intersect(f, f, 4)["result"] == q.INTERSECTION
