@@ -275,6 +275,31 @@ typedef struct {
 } spk_ray_params;
 
 /*
+ * spk_intersect (Section 4.9): whether the solids {f < 0} and {g < 0} of two
+ * networks overlap inside the tree domain, by octree rounds (arity 8) that
+ * bound both networks on every frontier cell: a cell with either function
+ * POSITIVE cannot hold a common point and is dropped; a cell with both
+ * NEGATIVE lies inside both solids and ends the search (witness: the
+ * smallest Morton code among such cells of that level); other cells split
+ * until tree->max_level, where they remain undecided.  Synchronous; the
+ * frontier buffers (74 bytes per cell) are stream-ordered within the
+ * context's workspace limit (SPK_E_NOMEM beyond it).
+ */
+enum { SPK_NO_INTERSECTION = 0, SPK_INTERSECTION = 1, SPK_INTERSECTION_UNDECIDED = 2 };
+typedef struct {
+  int32_t result;           /* SPK_NO_INTERSECTION / SPK_INTERSECTION / _UNDECIDED */
+  int32_t level;            /* witness level (SPK_INTERSECTION), else -1          */
+  uint64_t cell;            /* witness Morton code                                */
+  int64_t undecided;        /* cells left at max_level (_UNDECIDED)               */
+  int64_t cells_bounded;    /* cell bounds evaluated (both networks)              */
+  int32_t rounds;
+  int32_t reserved;
+} spk_intersect_result;
+
+spk_status spk_intersect(spk_ctx* ctx, const spk_net* net_f, const spk_net* net_g, const spk_bound_opts* opts,
+                         const spk_tree_params* tree, spk_intersect_result* out);
+
+/*
  * spk_empty_spheres (Section 4.4): for each point p_i (dev [n][3]) the first
  * radius r in r0, r0/2, r0/4, ... with r >= r_min such that the bound
  * classifies the cube [p - r, p + r]^3 (rounded outwards) as POSITIVE or

@@ -862,6 +862,99 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
   return check_hip(hipStreamSynchronize(ctx->stream));
 }
 
+// Intersection of two shapes (Section 4.9); the combine kernel is in
+// intersect.hip.
+spk_status spk_intersect(spk_ctx* ctx, const spk_net* net_f, const spk_net* net_g, const spk_bound_opts* opts,
+                         const spk_tree_params* tree, spk_intersect_result* out) {
+  if (ctx == nullptr || net_f == nullptr || net_g == nullptr || tree == nullptr || out == nullptr) return SPK_E_INVAL;
+  spk_status st = valid_opts(opts);
+  if (st != SPK_OK) return st;
+  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
+  if (tree->max_level < 0 || tree->max_level > 20) return SPK_E_INVAL;
+  for (int d = 0; d < 3; ++d)
+    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
+      return SPK_E_INVAL;
+  void *cells = nullptr, *kids = nullptr, *lf = nullptr, *lg = nullptr, *cnt = nullptr;
+  size_t c_cells = 0, c_kids = 0, c_lf = 0, c_lg = 0, c_cnt = 0;
+  CallBuffers B;
+  B.limit = ctx->workspace_limit;
+  B.stream = ctx->stream;
+  B.peak = &ctx->ws_peak;
+#define SPK_IX_ENSURE(ptr, cap, bytes)              \
+  do {                                              \
+    spk_status e_ = B.ensure(&(ptr), cap, (bytes)); \
+    if (e_ != SPK_OK) return e_;                    \
+  } while (0)
+  SPK_IX_ENSURE(cells, c_cells, 8);
+  SPK_IX_ENSURE(cnt, c_cnt, 256);
+  if (hipMemsetAsync(cells, 0, 8, ctx->stream) != hipSuccess) return SPK_E_DEVICE;   // the root
+  *out = spk_intersect_result{};
+  out->result = SPK_NO_INTERSECTION;
+  out->level = -1;
+  int64_t m = 1;
+  for (int level = 0; level <= tree->max_level; ++level) {
+    const bool at_max = level == tree->max_level;
+    SPK_IX_ENSURE(lf, c_lf, (size_t)m);
+    SPK_IX_ENSURE(lg, c_lg, (size_t)m);
+    if (!at_max) SPK_IX_ENSURE(kids, c_kids, (size_t)m * 64);
+    for (int w = 0; w < 2; ++w) {
+      BoundJob job = {};
+      job.n = m;
+      job.mode = IN_CELL;
+      job.s = 3;
+      job.policy = opts->policy;
+      job.k = opts->k;
+      job.prec = opts->prec;
+      job.rigorous = rigorous_opts(opts) ? 1 : 0;
+      job.cells = (const uint64_t*)cells;
+      job.level = level;
+      for (int d = 0; d < 3; ++d) {
+        job.dom_lo[d] = tree->dom_lo[d];
+        job.dom_hi[d] = tree->dom_hi[d];
+      }
+      job.label = (uint8_t*)(w == 0 ? lf : lg);
+      st = launch_bound(w == 0 ? net_f : net_g, job, ctx->stream, ctx->num_cus);
+      if (st != SPK_OK) return st;
+    }
+    IxRound X = {};
+    X.n = m;
+    X.at_max = at_max ? 1 : 0;
+    X.cells = (const uint64_t*)cells;
+    X.lab_f = (const uint8_t*)lf;
+    X.lab_g = (const uint8_t*)lg;
+    X.children = (uint64_t*)kids;
+    X.cap = at_max ? 0 : m * 8;
+    X.counts = (unsigned long long*)cnt;
+    st = launch_ix_round(X, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+    unsigned long long c[4] = {0ull, 0ull, 0ull, 0ull};
+    if (hipMemcpyAsync(c, cnt, sizeof(c), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return SPK_E_DEVICE;
+    out->cells_bounded += 2 * m;
+    out->rounds = level + 1;
+    if (c[3] > 0) {
+      out->result = SPK_INTERSECTION;
+      out->level = level;
+      out->cell = c[2];
+      break;
+    }
+    if (at_max) {
+      out->undecided = (int64_t)c[1];
+      out->result = c[1] > 0 ? SPK_INTERSECTION_UNDECIDED : SPK_NO_INTERSECTION;
+      break;
+    }
+    if (c[0] == 0) break;   // every cell dropped
+    m = (int64_t)c[0];
+    std::swap(cells, kids);
+    std::swap(c_cells, c_kids);
+  }
+#undef SPK_IX_ENSURE
+  net_mark_use(net_f, ctx->stream);
+  net_mark_use(net_g, ctx->stream);
+  return SPK_OK;
+}
+
 // Empty spheres (Section 4.4); kernels in spheres.hip.
 spk_status spk_empty_spheres(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts, int64_t n, const float* p,
                              float r0, float r_min, float* radius, uint8_t* label) {

@@ -131,6 +131,19 @@ struct CpDive {
   float* point;              // [n][3] candidates
 };
 
+// One round of the two-shape intersection test (intersect.hip).
+struct IxRound {
+  int64_t n;
+  int32_t at_max;
+  int32_t pad;
+  const uint64_t* cells;     // [n] frontier
+  const uint8_t* lab_f;      // [n] classification by f
+  const uint8_t* lab_g;      // [n] classification by g
+  uint64_t* children;        // [cap]
+  int64_t cap;
+  unsigned long long* counts;   // [4]
+};
+
 // Empty-sphere rounds (spheres.hip).
 struct EsRound {
   int64_t n;
@@ -264,6 +277,7 @@ spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t str
 // labelled cells of every item (one launch each).
 hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix, int n_items, int blocks,
                                 hipStream_t stream);
+spk_status launch_ix_round(const IxRound& X, hipStream_t stream, int num_cus);
 spk_status launch_es_init(const EsRound& E, hipStream_t stream);
 spk_status launch_es_boxes(const EsRound& E, int64_t m, hipStream_t stream);
 spk_status launch_es_update(const EsRound& E, int64_t m, hipStream_t stream);

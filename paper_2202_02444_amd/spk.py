@@ -24,7 +24,7 @@ UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
            "spk_subdivide_frontier", "spk_subdivide_frontier_noalloc", "spk_cast_rays", "spk_cast_frusta",
-           "spk_empty_spheres",
+           "spk_empty_spheres", "spk_intersect",
            "spk_eval_points", "spk_closest_point",
            "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
            "spk_batch_destroy", "spk_server_create", "spk_server_submit", "spk_server_poll",
@@ -75,6 +75,15 @@ class Camera(ctypes.Structure):
 class FrustumStats(ctypes.Structure):
     _fields_ = [("frustum_steps", ctypes.c_int64), ("rays_handed_off", ctypes.c_int64),
                 ("ray_iterations", ctypes.c_int64), ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class IntersectResult(ctypes.Structure):
+    _fields_ = [("result", ctypes.c_int32), ("level", ctypes.c_int32), ("cell", ctypes.c_uint64),
+                ("undecided", ctypes.c_int64), ("cells_bounded", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+NO_INTERSECTION, INTERSECTION, INTERSECTION_UNDECIDED = 0, 1, 2
 
 
 class TreeParams(ctypes.Structure):
@@ -132,6 +141,8 @@ def lib():
         L.spk_subdivide_frontier_noalloc.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
+        L.spk_intersect.argtypes = [vp, vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams),
+                                    ctypes.POINTER(IntersectResult)]
         L.spk_empty_spheres.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, vp, ctypes.c_float,
                                         ctypes.c_float, vp, vp]
         L.spk_cast_frusta.argtypes = [vp, vp, ctypes.POINTER(RayParams), ctypes.POINTER(BoundOpts),
@@ -343,6 +354,18 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
                              _ptr(direction, torch.float32, (n, 3), "direction"),
                              _ptr(t_hit, torch.float32, (n,), "t_hit"), _ptr(iters, torch.int32, (n,), "iters"))
     _check(st, "spk_cast_rays")
+
+
+def intersect(ctx, net_f, net_g, max_level=8, policy="truncate", k=31, rigorous=True, prec="f32",
+              dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0)):
+    """spk_intersect: whether the solids {f < 0} and {g < 0} overlap."""
+    tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), 8)
+    o = opts(policy, k, rigorous, prec)
+    r = IntersectResult()
+    _check(lib().spk_intersect(ctx.handle, net_f.handle, net_g.handle, ctypes.byref(o), ctypes.byref(tp),
+                               ctypes.byref(r)), "spk_intersect")
+    return {"result": int(r.result), "level": int(r.level), "cell": int(r.cell), "undecided": int(r.undecided),
+            "cells_bounded": int(r.cells_bounded), "rounds": int(r.rounds)}
 
 
 def empty_spheres(ctx, net, p, radius, label, r0=1.0, r_min=1e-4, policy="truncate", k=31, rigorous=True,

@@ -131,6 +131,21 @@ def test_tree_and_ray_validation():
     assert spk.ray_params(rigorous=False).flags == spk.FLAG_NO_ROUNDING_BOUND and spk.ray_params().flags == 0
 
 
+def test_intersect_validation():
+    L = spk.lib()
+    o = spk.opts("truncate", 31)
+    r = spk.IntersectResult()
+    tp = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 4, 8)
+    assert L.spk_intersect(FAKE, FAKE, None, ctypes.byref(o), ctypes.byref(tp), ctypes.byref(r)) == spk.E_INVAL
+    assert L.spk_intersect(FAKE, FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), None) == spk.E_INVAL
+    kd = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 4, 2)
+    assert L.spk_intersect(FAKE, FAKE, FAKE, ctypes.byref(o), ctypes.byref(kd), ctypes.byref(r)) == spk.E_UNSUPPORTED
+    deep = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 21, 8)
+    assert L.spk_intersect(FAKE, FAKE, FAKE, ctypes.byref(o), ctypes.byref(deep), ctypes.byref(r)) == spk.E_INVAL
+    empty = spk.TreeParams((ctypes.c_float * 3)(1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 4, 8)
+    assert L.spk_intersect(FAKE, FAKE, FAKE, ctypes.byref(o), ctypes.byref(empty), ctypes.byref(r)) == spk.E_INVAL
+
+
 def test_empty_spheres_validation():
     L = spk.lib()
     o = spk.opts("truncate", 31)
@@ -245,6 +260,7 @@ def test_struct_layouts_match_the_header(tmp_path):
                "spk_ray_params": spk.RayParams, "spk_batch_item": spk.BatchItem, "spk_batch_class": spk.BatchClass,
                "spk_request": spk.Request, "spk_completion": spk.Completion,
                "spk_device_status": spk.DeviceStatus, "spk_camera": spk.Camera,
+               "spk_intersect_result": spk.IntersectResult,
                "spk_frustum_stats": spk.FrustumStats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "spk.h"', "int main(void) {"]
     for cname, py in structs.items():

@@ -462,3 +462,54 @@ def test_empty_spheres_vs_oracle(ctx, netname, rigorous):
     f = omlp.forward(net, P.reshape(-1, 3)).reshape(ok.size, -1)
     pos = lg[ok] == spk.POSITIVE
     assert np.all(f[pos] > 0) and np.all(f[~pos] < 0)
+
+
+def _octa_at(a, R, width=32):
+    """|x - a|_1 - R as an exact ReLU network, the hidden layer padded with
+    zero neurons to a supported width."""
+    a = np.asarray(a, dtype=np.float32)
+    W1 = np.zeros((width, 3), np.float32)
+    W1[:3], W1[3:6] = np.eye(3), -np.eye(3)
+    b1 = np.zeros(width, np.float32)
+    b1[:3], b1[3:6] = -a, a
+    W2 = np.zeros((1, width), np.float32)
+    W2[0, :6] = 1.0
+    return wl.MLPSpec([W1, W2], [b1, np.array([-R], np.float32)], act="relu")
+
+
+@pytest.mark.parametrize("rigorous", [False, True])
+def test_intersect_vs_oracle(ctx, rigorous):
+    """Section 4.9 on pairs of networks: exact octahedra (overlapping,
+    separated, touching) and random pairs.  In the paper's arithmetic the
+    result, witness level and cell and undecided count equal the oracle's
+    (the networks' bounds are far from the tolerance band here); in the
+    rounding-bounded mode a witness is found at the oracle's level or later
+    and a NO_INTERSECTION answer appears only where the oracle has one.  Every
+    GPU witness cell lies inside both solids (FP64 samples)."""
+    from paper_2202_02444_amd import spk
+    pairs = [(_octa_at([-0.25, 0, 0], 0.35), _octa_at([0.25, 0, 0], 0.35), 6),
+             (_octa_at([-0.45, 0, 0], 0.35), _octa_at([0.45, 0, 0], 0.35), 6),
+             (_octa_at([-0.35, 0, 0], 0.35), _octa_at([0.35, 0, 0], 0.35), 5),
+             (wl.tiny_net(0), wl.tiny_net(3), 6),
+             (wl.he_normal_mlp([3, 64, 64, 1], 60, act="relu", bias=0.4),
+              wl.he_normal_mlp([3, 64, 64, 1], 61, act="relu", bias=0.4), 6)]
+    rng = np.random.default_rng(2)
+    for f, g, depth in pairs:
+        gf, gg = spk.Net.from_spec(f), spk.Net.from_spec(g)
+        r = spk.intersect(ctx, gf, gg, depth, rigorous=rigorous)
+        o = oq.intersect(f, g, depth)
+        if not rigorous:
+            assert (r["result"], r["level"], r["cell"], r["undecided"]) == \
+                (o["result"], o["level"], o["cell"], o["undecided"]), (r, o)
+        else:
+            if r["result"] == spk.INTERSECTION:
+                assert o["result"] == oq.INTERSECTION and r["level"] >= o["level"]
+            if r["result"] == spk.NO_INTERSECTION:
+                assert o["result"] == oq.NO_INTERSECTION
+        if r["result"] == spk.INTERSECTION:
+            lo, hi = oq.cell_bounds(np.array([r["cell"]], dtype=np.uint64), r["level"], (-1,) * 3, (1,) * 3)
+            from parity import sample_points
+            P = sample_points(lo, hi, rng, 24).reshape(-1, 3)
+            assert np.all(omlp.forward(f, P) < 0) and np.all(omlp.forward(g, P) < 0)
+        gf.close()
+        gg.close()
