@@ -211,12 +211,19 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
                               const float* box_lo, const float* box_hi, uint8_t* label, float* lo,
                               float* hi, const spk_bound_aux* aux);
 
-/* Tree parameters: the domain box and the fixed maximum octree level. */
+/* Tree parameters: the domain box and the fixed maximum octree level.
+ * delta > 0 turns on the convergence test of Procedure 3 for small cells
+ * (spk_subdivide_frontier only; the other calls require 0): at a level whose
+ * cells' widest side is below delta / sqrt(3), an UNKNOWN cell whose six face
+ * centers show both signs of f (FP32 evaluation) is within delta of the level
+ * set and final; it goes to `leaves` instead of splitting. */
 typedef struct {
   float dom_lo[3];
   float dom_hi[3];
   int32_t max_level;   /* 0 <= max_level <= 20                                   */
   int32_t arity;       /* 8 (octree); other values give SPK_E_UNSUPPORTED        */
+  float delta;         /* 0: fixed depth; > 0: convergence test (finite)         */
+  int32_t reserved;
 } spk_tree_params;
 
 /*
@@ -225,7 +232,9 @@ typedef struct {
  * y at 3b+1, z at 3b+2).  Each cell is classified; POSITIVE and NEGATIVE cells
  * are counted; UNKNOWN cells with level < max_level write their 8 children
  * (code << 3 | octant) to `children`; UNKNOWN cells at max_level are copied to
- * `leaves` (the cells handed to mesh extraction, Section 4.7).
+ * `leaves` (the cells handed to mesh extraction, Section 4.7), and so are the
+ * converged cells of the delta test (tree->delta > 0; not available in
+ * spk_subdivide_frontier_noalloc, SPK_E_UNSUPPORTED).
  *   children dev [cap_children], leaves dev [cap_leaves] (either may be NULL
  *            when its capacity is 0).
  *   counts   dev int64 [4]: n_children, n_leaves, n_pos, n_neg.  The call sets

@@ -113,7 +113,7 @@ def kd_bounds(code, depth, dom_lo, dom_hi):
 
 
 def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1),
-                 arity=8, keep_leaf_lists=False, max_cells=None):
+                 arity=8, keep_leaf_lists=False, max_cells=None, delta=None):
     """Fixed-depth BuildSpatialTree in parallel rounds.
 
     Each round classifies every cell of the current level: POSITIVE and
@@ -122,9 +122,15 @@ def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), d
     midpoint); UNKNOWN cells at ``max_level`` form the leaf list handed to mesh
     extraction.  Returns a dict with per-level frontier sizes and counts, the
     sorted UNKNOWN leaf codes and (optionally) the POSITIVE/NEGATIVE leaves.
+
+    With ``delta`` (octree only) the convergence test of Procedure 3 applies:
+    at a level whose cells' widest side is below delta / sqrt(3), an UNKNOWN
+    cell whose six face centers show both signs of f is final (within delta of
+    the level set); ``converged`` then lists (level, sorted codes).
     """
     codes = np.zeros(1, dtype=np.uint64)
     levels = []
+    converged = []
     pos_leaves, neg_leaves = [], []
     unk_leaves = np.zeros(0, dtype=np.uint64)
     for level in range(max_level + 1):
@@ -138,8 +144,19 @@ def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), d
         else:
             lab = np.zeros(0, dtype=np.uint8)
         unk = codes[lab == UNKNOWN]
+        n_conv = 0
+        if delta is not None and arity == 8 and unk.size and \
+                np.max(np.asarray(dom_hi, dtype=np.float64) - np.asarray(dom_lo, dtype=np.float64)) / 2.0 ** level \
+                < delta / math.sqrt(3.0):
+            ulo, uhi = lo[lab == UNKNOWN], hi[lab == UNKNOWN]
+            pts = np.stack([face_centers(ulo[j], uhi[j]) for j in range(unk.size)])   # [m, 6, 3]
+            fv = mlp.forward(net, pts.reshape(-1, 3)).reshape(unk.size, 6)
+            span = np.any(fv < 0.0, axis=1) & np.any(fv > 0.0, axis=1)
+            converged.append((level, np.sort(unk[span])))
+            n_conv = int(span.sum())
+            unk = unk[~span]
         levels.append({"level": level, "n": int(codes.size), "n_pos": int((lab == POSITIVE).sum()),
-                       "n_neg": int((lab == NEGATIVE).sum()), "n_unk": int(unk.size)})
+                       "n_neg": int((lab == NEGATIVE).sum()), "n_unk": int(unk.size), "n_conv": n_conv})
         if keep_leaf_lists:
             pos_leaves.append((level, codes[lab == POSITIVE]))
             neg_leaves.append((level, codes[lab == NEGATIVE]))
@@ -151,7 +168,7 @@ def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), d
         codes = np.sort(np.concatenate(kids)) if unk.size else np.zeros(0, dtype=np.uint64)
         if max_cells is not None and codes.size > max_cells:
             raise RuntimeError("frontier exceeds max_cells")
-    return {"levels": levels, "leaves": unk_leaves, "pos": pos_leaves, "neg": neg_leaves}
+    return {"levels": levels, "leaves": unk_leaves, "pos": pos_leaves, "neg": neg_leaves, "converged": converged}
 
 
 # ---------------------------------------------------------------------------

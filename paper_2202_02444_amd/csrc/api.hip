@@ -520,10 +520,21 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
 
 // One frontier round given the per-cell label buffer `labels` (n bytes of
 // device memory the call may overwrite).
+// Whether the convergence test applies at `level`: the cells' widest side is
+// below delta / sqrt(3).
+static bool converge_level(const spk_tree_params* tree, int32_t level) {
+  if (!(tree->delta > 0.0f)) return false;
+  double side = 0.0;
+  for (int d = 0; d < 3; ++d)
+    side = fmax(side, ((double)tree->dom_hi[d] - (double)tree->dom_lo[d]) / (double)(1u << level));
+  return side < (double)tree->delta / 1.7320508075688772;
+}
+
+// `faces` (nullable): 96 bytes per cell for the convergence test.
 static spk_status subdivide_round(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
                                   const spk_tree_params* tree, int32_t level, const uint64_t* cells, int64_t n,
                                   uint64_t* children, int64_t cap_children, uint64_t* leaves, int64_t cap_leaves,
-                                  int64_t* counts, uint8_t* labels) {
+                                  int64_t* counts, uint8_t* labels, float* faces = nullptr) {
   BoundJob job = {};
   job.n = n;
   job.mode = IN_CELL;
@@ -543,6 +554,11 @@ static spk_status subdivide_round(spk_ctx* ctx, const spk_net* net, const spk_bo
   if (n > 0) {
     spk_status st = launch_bound(net, job, ctx->stream, ctx->num_cus);
     if (st != SPK_OK) return st;
+    if (faces != nullptr) {
+      st = launch_converge(net, labels, cells, n, level, tree->dom_lo, tree->dom_hi, faces, faces + 18 * n,
+                           ctx->stream, ctx->num_cus);
+      if (st != SPK_OK) return st;
+    }
   }
   return launch_compact(labels, cells, n, level == tree->max_level, children, cap_children, leaves, cap_leaves,
                         counts, ctx->status, ctx->stream, ctx->num_cus);
@@ -560,6 +576,7 @@ static spk_status check_subdivide_args(spk_ctx* ctx, const spk_net* net, const s
   for (int d = 0; d < 3; ++d)
     if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
       return SPK_E_INVAL;
+  if (!(tree->delta >= 0.0f) || !isfinite(tree->delta)) return SPK_E_INVAL;
   if (n < 0 || cap_children < 0 || cap_leaves < 0) return SPK_E_INVAL;
   if (n > 0 && cells == nullptr) return SPK_E_INVAL;
   if ((cap_children > 0 && children == nullptr) || (cap_leaves > 0 && leaves == nullptr)) return SPK_E_INVAL;
@@ -574,12 +591,18 @@ spk_status spk_subdivide_frontier(spk_ctx* ctx, const spk_net* net, const spk_bo
                                        cap_leaves, counts);
   if (st != SPK_OK) return st;
   void* labels = nullptr;
+  float* faces = nullptr;
   if (n > 0) {
-    st = ctx_scratch(ctx, (size_t)n, &labels);
+    // labels, then (for the convergence test) 18 face coordinates and 6
+    // values per cell
+    const bool conv = converge_level(tree, level);
+    const size_t lab_bytes = ((size_t)n + 255) & ~(size_t)255;
+    st = ctx_scratch(ctx, lab_bytes + (conv ? (size_t)n * 96 : 0), &labels);
     if (st != SPK_OK) return st;
+    if (conv) faces = (float*)((char*)labels + lab_bytes);
   }
   st = subdivide_round(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves, cap_leaves, counts,
-                       (uint8_t*)labels);
+                       (uint8_t*)labels, faces);
   if (st == SPK_OK) net_mark_use(net, ctx->stream);
   return st;
 }
@@ -591,6 +614,7 @@ spk_status spk_subdivide_frontier_noalloc(spk_ctx* ctx, const spk_net* net, cons
   spk_status st = check_subdivide_args(ctx, net, opts, tree, level, cells, n, children, cap_children, leaves,
                                        cap_leaves, counts);
   if (st != SPK_OK) return st;
+  if (tree->delta != 0.0f) return SPK_E_UNSUPPORTED;   // its face buffers would need an allocation
   if (n > (int64_t)SPK_NOALLOC_MAX_CELLS) return SPK_E_LIMIT;
   void* labels = nullptr;
   st = noalloc_scratch(ctx->device, &labels);
@@ -832,7 +856,7 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
   spk_status st = valid_opts(opts);
   if (st != SPK_OK) return st;
   if (tree->arity != 8) return SPK_E_UNSUPPORTED;
-  if (tree->max_level < 0 || tree->max_level > 20) return SPK_E_INVAL;
+  if (tree->max_level < 0 || tree->max_level > 20 || tree->delta != 0.0f) return SPK_E_INVAL;
   for (int d = 0; d < 3; ++d)
     if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
       return SPK_E_INVAL;
@@ -870,7 +894,7 @@ spk_status spk_intersect(spk_ctx* ctx, const spk_net* net_f, const spk_net* net_
   spk_status st = valid_opts(opts);
   if (st != SPK_OK) return st;
   if (tree->arity != 8) return SPK_E_UNSUPPORTED;
-  if (tree->max_level < 0 || tree->max_level > 20) return SPK_E_INVAL;
+  if (tree->max_level < 0 || tree->max_level > 20 || tree->delta != 0.0f) return SPK_E_INVAL;
   for (int d = 0; d < 3; ++d)
     if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
       return SPK_E_INVAL;

@@ -60,31 +60,6 @@ __global__ __launch_bounds__(256) void cp_init_kernel(int64_t n, uint64_t* codes
   }
 }
 
-// The 6 face centers of a cell (the cell center with one coordinate moved to
-// a face), written as 18 floats.  The level rounds and the seeding descent
-// both use this, so a cell's spanning test is the same in either.
-__device__ __forceinline__ void write_faces(const float (&lo)[3], const float (&hi)[3], float* out) {
-  float c[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) c[d] = 0.5f * (lo[d] + hi[d]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) out[(2 * a + sd) * 3 + d] = (d == a) ? (sd ? hi[d] : lo[d]) : c[d];
-}
-
-__device__ __forceinline__ bool spans6(const float* v) {
-  bool neg = false, pos = false;
-#pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    neg = neg || v[p] < 0.0f;
-    pos = pos || v[p] > 0.0f;
-  }
-  return neg && pos;
-}
-
 // Face centers of every frontier cell.
 __global__ __launch_bounds__(256) void cp_faces_kernel(CpLevel L) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.m; i += (int64_t)gridDim.x * blockDim.x) {

@@ -92,6 +92,40 @@ __device__ __forceinline__ void cell_box(uint64_t code, int level, const float (
   }
 }
 
+// The 6 face centers of a cell (the cell center with one coordinate moved to
+// a face), as 18 floats; the closest-point rounds, their seeding descent and
+// the convergence test of the frontier rounds share it, so a cell's spanning
+// test is the same everywhere.
+__device__ __forceinline__ void write_faces(const float (&lo)[3], const float (&hi)[3], float* out) {
+  float c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) c[d] = 0.5f * (lo[d] + hi[d]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) out[(2 * a + sd) * 3 + d] = (d == a) ? (sd ? hi[d] : lo[d]) : c[d];
+}
+
+// Whether six face values show both signs.
+__device__ __forceinline__ bool spans6(const float* v) {
+  bool neg = false, pos = false;
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    neg = neg || v[p] < 0.0f;
+    pos = pos || v[p] > 0.0f;
+  }
+  return neg && pos;
+}
+
+struct CellDom {
+  float lo[3], hi[3];
+};
+
+// Internal label of a frontier cell that passed the convergence test.
+constexpr uint8_t kConverged = 3;
+
 // One round of the closest-point search (closest.hip): the frontier of
 // (query, cell) pairs at `level` and its outputs.
 struct CpLevel {
@@ -277,6 +311,11 @@ spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t str
 // labelled cells of every item (one launch each).
 hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix, int n_items, int blocks,
                                 hipStream_t stream);
+// The convergence test of a frontier round: face centers of every cell,
+// their f, and UNKNOWN cells that span the level set relabelled kConverged.
+spk_status launch_converge(const spk_net* net, uint8_t* labels, const uint64_t* cells, int64_t n, int level,
+                           const float (&dom_lo)[3], const float (&dom_hi)[3], float* fpts, float* fvals,
+                           hipStream_t stream, int num_cus);
 spk_status launch_ix_round(const IxRound& X, hipStream_t stream, int num_cus);
 spk_status launch_es_init(const EsRound& E, hipStream_t stream);
 spk_status launch_es_boxes(const EsRound& E, int64_t m, hipStream_t stream);

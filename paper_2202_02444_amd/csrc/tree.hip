@@ -21,31 +21,71 @@ __device__ __forceinline__ void compact_chunk(const uint8_t* __restrict__ labels
   const bool in = i < n;
   const uint8_t lab = in ? labels[i] : (uint8_t)255;
   const bool unk = lab == SPK_UNKNOWN;
-  const unsigned long long mu = __ballot(unk);
+  // converged cells (the delta test) and UNKNOWN cells at the maximum level
+  // are leaves; other UNKNOWN cells split
+  const bool to_leaf = lab == kConverged || (at_max && unk);
+  const bool to_kids = !at_max && unk;
+  const unsigned long long mk = __ballot(to_kids);
+  const unsigned long long ml = __ballot(to_leaf);
   const unsigned long long mp = __ballot(lab == SPK_POSITIVE);
   const unsigned long long mn = __ballot(lab == SPK_NEGATIVE);
-  const int nu = __popcll(mu);
-  unsigned long long off = 0ull;
+  unsigned long long offk = 0ull, offl = 0ull;
   if (lane == 0) {
-    if (nu) off = atomicAdd(&counts[at_max ? 1 : 0], (unsigned long long)(at_max ? nu : 8 * nu));
+    if (mk) offk = atomicAdd(&counts[0], 8ull * (unsigned long long)__popcll(mk));
+    if (ml) offl = atomicAdd(&counts[1], (unsigned long long)__popcll(ml));
     if (mp) atomicAdd(&counts[2], (unsigned long long)__popcll(mp));
     if (mn) atomicAdd(&counts[3], (unsigned long long)__popcll(mn));
   }
-  off = __shfl(off, 0, 64);
-  if (unk) {
-    const int64_t pre = __popcll(mu & below);
+  offk = __shfl(offk, 0, 64);
+  offl = __shfl(offl, 0, 64);
+  if (to_leaf) {
+    const int64_t p = (int64_t)offl + __popcll(ml & below);
+    if (p < cap_leaves) leaves[p] = cells[i];
+  } else if (to_kids) {
+    const int64_t pre = __popcll(mk & below);
     const uint64_t code = cells[i];
-    if (at_max) {
-      const int64_t p = (int64_t)off + pre;
-      if (p < cap_leaves) leaves[p] = code;
-    } else {
 #pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        const int64_t p = (int64_t)off + 8 * pre + o;
-        if (p < cap_children) children[p] = (code << 3) | (uint64_t)o;
-      }
+    for (int o = 0; o < 8; ++o) {
+      const int64_t p = (int64_t)offk + 8 * pre + o;
+      if (p < cap_children) children[p] = (code << 3) | (uint64_t)o;
     }
   }
+}
+
+// The convergence test (Procedure 3, small cells): face centers of every
+// cell, then UNKNOWN cells whose face values show both signs become
+// kConverged.
+__global__ __launch_bounds__(256) void converge_faces_kernel(const uint64_t* cells, int64_t n, int level, CellDom dom,
+                                                             float* fpts) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float lo[3], hi[3];
+    cell_box(cells[i], level, dom.lo, dom.hi, lo, hi);
+    write_faces(lo, hi, fpts + 18 * i);
+  }
+}
+
+__global__ __launch_bounds__(256) void converge_mark_kernel(uint8_t* labels, int64_t n, const float* fvals) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (labels[i] == SPK_UNKNOWN && spans6(fvals + 6 * i)) labels[i] = kConverged;
+}
+
+spk_status launch_converge(const spk_net* net, uint8_t* labels, const uint64_t* cells, int64_t n, int level,
+                           const float (&dom_lo)[3], const float (&dom_hi)[3], float* fpts, float* fvals,
+                           hipStream_t stream, int num_cus) {
+  if (n <= 0) return SPK_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)num_cus * 8) blocks = (int64_t)num_cus * 8;
+  CellDom dom;
+  for (int d = 0; d < 3; ++d) {
+    dom.lo[d] = dom_lo[d];
+    dom.hi[d] = dom_hi[d];
+  }
+  hipLaunchKernelGGL(converge_faces_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, cells, n, level, dom, fpts);
+  if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
+  spk_status st = launch_eval(net, 6 * n, fpts, fvals, stream, num_cus);
+  if (st != SPK_OK) return st;
+  hipLaunchKernelGGL(converge_mark_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, labels, n, fvals);
+  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
 }
 
 __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict__ labels,

@@ -88,7 +88,7 @@ NO_INTERSECTION, INTERSECTION, INTERSECTION_UNDECIDED = 0, 1, 2
 
 class TreeParams(ctypes.Structure):
     _fields_ = [("dom_lo", ctypes.c_float * 3), ("dom_hi", ctypes.c_float * 3), ("max_level", ctypes.c_int32),
-                ("arity", ctypes.c_int32)]
+                ("arity", ctypes.c_int32), ("delta", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
 class RayParams(ctypes.Structure):
@@ -317,11 +317,13 @@ def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=Non
 
 def subdivide_frontier(ctx, net, level, cells, children, leaves, counts, max_level, policy="truncate", k=31,
                        dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8, noalloc=False, rigorous=True,
-                       prec="f32"):
+                       prec="f32", delta=0.0):
     """One round of Procedure 3 (spk_subdivide_frontier, or with
-    noalloc=True spk_subdivide_frontier_noalloc)."""
+    noalloc=True spk_subdivide_frontier_noalloc); delta > 0 adds the
+    convergence test for small cells."""
     import torch
-    tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), int(arity))
+    tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), int(arity),
+                    float(delta), 0)
     o = opts(policy, k, rigorous, prec)
     n = cells.shape[0]
     capc = children.shape[0] if children is not None else 0
@@ -595,6 +597,36 @@ def eval_points(ctx, net, x, f):
     st = lib().spk_eval_points(ctx.handle, net.handle, n, _ptr(x, torch.float32, (n, 3), "x"),
                                _ptr(f, torch.float32, (n,), "f"))
     _check(st, "spk_eval_points")
+
+
+def build_delta_tree(ctx, net, delta, max_level=20, policy="truncate", k=31, rigorous=True, prec="f32",
+                     dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3):
+    """BuildSpatialTree with the convergence test (Procedure 3): octree rounds
+    in which, once cells are smaller than delta / sqrt(3), UNKNOWN cells whose
+    face centers show both signs are final leaves (within delta of the level
+    set).  Returns per-level stats and the leaves per level (a list of GPU
+    tensors of Morton codes, converged cells and the cells left at
+    max_level)."""
+    import torch
+    dev = torch.device("cuda")
+    cells = torch.zeros(1, dtype=torch.int64, device=dev)
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    levels, leaves = [], []
+    for level in range(max_level + 1):
+        n = cells.shape[0]
+        if n == 0:
+            break
+        at_max = level == max_level
+        children = None if at_max else torch.empty(8 * n, dtype=torch.int64, device=dev)
+        lv = torch.empty(n, dtype=torch.int64, device=dev)
+        subdivide_frontier(ctx, net, level, cells, children, lv, counts, max_level, policy, k, dom_lo, dom_hi,
+                           rigorous=rigorous, prec=prec, delta=delta)
+        ctx.sync()
+        c = counts.cpu().tolist()
+        levels.append({"level": level, "n": n, "n_children": c[0], "n_leaves": c[1], "n_pos": c[2], "n_neg": c[3]})
+        leaves.append(lv[:c[1]])
+        cells = children[:c[0]] if children is not None else cells[:0]
+    return levels, leaves
 
 
 def build_octrees_batched(ctx, nets, max_level, policy="truncate", k=31, rigorous=True, tune=False,

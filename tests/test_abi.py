@@ -131,6 +131,25 @@ def test_tree_and_ray_validation():
     assert spk.ray_params(rigorous=False).flags == spk.FLAG_NO_ROUNDING_BOUND and spk.ray_params().flags == 0
 
 
+def test_delta_tree_validation():
+    L = spk.lib()
+    o = spk.opts("truncate", 31)
+    cnt = FAKE
+    tp = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8, 0.01, 0)
+    # the non-allocating round has no face buffers for the convergence test
+    assert L.spk_subdivide_frontier_noalloc(FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), 0, FAKE, 1, FAKE, 8,
+                                            None, 0, cnt) == spk.E_UNSUPPORTED
+    bad = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8, -1.0, 0)
+    assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(bad), 0, FAKE, 1, FAKE, 8, None, 0,
+                                    cnt) == spk.E_INVAL
+    # the other tree calls take no delta
+    r = spk.IntersectResult()
+    assert L.spk_intersect(FAKE, FAKE, FAKE, ctypes.byref(o), ctypes.byref(tp), ctypes.byref(r)) == spk.E_INVAL
+    fx = spk.opts("fixed", 0)
+    assert L.spk_closest_point(FAKE, FAKE, ctypes.byref(fx), ctypes.byref(tp), 4, FAKE, FAKE, None,
+                               None) == spk.E_INVAL
+
+
 def test_intersect_validation():
     L = spk.lib()
     o = spk.opts("truncate", 31)

@@ -513,3 +513,45 @@ def test_intersect_vs_oracle(ctx, rigorous):
             assert np.all(omlp.forward(f, P) < 0) and np.all(omlp.forward(g, P) < 0)
         gf.close()
         gg.close()
+
+
+@pytest.mark.parametrize("netname", ["octa", "tiny", "elu64"])
+def test_delta_tree_vs_oracle(ctx, netname):
+    """BuildSpatialTree with the convergence test (Procedure 3), paper
+    arithmetic: per level the frontier size and the POSITIVE, NEGATIVE and
+    converged counts equal the oracle's up to cells whose bound or face values
+    sit at rounding level, the converged cells are the oracle's, and on the
+    exact octahedron every converged cell holds a surface point and the
+    labelled cells tile the domain."""
+    from paper_2202_02444_amd import spk
+    net = {"octa": wl.octahedron_mlp(0.55, pad_to=32), "tiny": wl.tiny_net(0),
+           "elu64": wl.he_normal_mlp([3, 64, 64, 1], 41, act="elu", bias=-0.3)}[netname]
+    delta, depth = 0.08, 8
+    g = spk.Net.from_spec(net)
+    levels, leaves = spk.build_delta_tree(ctx, g, delta, depth, "truncate", 31, rigorous=False)
+    res = oq.octree_build(net, depth, "truncate", 31, delta=delta)
+    conv_o = {lv: c for lv, c in res["converged"]}
+    vol = 0.0
+    for lg, lo_ in zip(levels, res["levels"]):
+        n = max(lo_["n"], 1)
+        tol = max(4, n // 500)
+        assert abs(lg["n"] - lo_["n"]) <= tol, (lg, lo_)
+        assert abs(lg["n_pos"] - lo_["n_pos"]) <= tol and abs(lg["n_neg"] - lo_["n_neg"]) <= tol
+        at_max = lg["level"] == depth
+        n_conv_g = lg["n_leaves"] if not at_max else None
+        if n_conv_g is not None:
+            assert abs(n_conv_g - lo_["n_conv"]) <= tol, (lg, lo_)
+            got = np.sort(leaves[lg["level"]].cpu().numpy().astype(np.uint64))
+            want = conv_o.get(lg["level"], np.zeros(0, np.uint64))
+            assert np.setxor1d(got, want).size <= tol
+        vol += (lg["n_pos"] + lg["n_neg"] + lg["n_leaves"]) * 8.0 ** -lg["level"]
+    assert vol == 1.0
+    if netname == "octa":
+        for lg in levels:
+            if lg["n_leaves"] and lg["level"] < depth:
+                codes = leaves[lg["level"]].cpu().numpy().astype(np.uint64)
+                lo, hi = oq.cell_bounds(codes, lg["level"], (-1,) * 3, (1,) * 3)
+                mx = np.maximum(np.abs(lo), np.abs(hi)).sum(axis=1)
+                mn = np.where((lo <= 0) & (hi >= 0), 0.0, np.minimum(np.abs(lo), np.abs(hi))).sum(axis=1)
+                assert np.all(mn <= 0.55 + 1e-6) and np.all(mx >= 0.55 - 1e-6)
+    g.close()

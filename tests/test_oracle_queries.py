@@ -383,3 +383,26 @@ def test_intersect_octahedra_closed_form():
     # a shape against itself: inside both wherever it is inside
     f = _octa_at([0.1, 0.0, 0.0], 0.5)
     assert q.intersect(f, f, 4)["result"] == q.INTERSECTION
+
+
+def test_delta_tree_octahedron():
+    """The convergence test of Procedure 3 on the exact octahedron: every
+    converged cell is smaller than delta / sqrt(3) in each side and contains a
+    point of the surface (closed-form range of |x|_1), so it lies within
+    delta of the level set; POSITIVE, NEGATIVE, converged and max-level cells
+    tile the domain exactly; and a larger delta converges at a coarser level."""
+    R = 0.55
+    net = wl.octahedron_mlp(R)
+    for delta, first in ((0.2, 5), (0.05, 7)):
+        res = q.octree_build(net, 9, "fixed", 0, delta=delta)
+        assert res["converged"] and res["converged"][0][0] == first
+        vol = 0.0
+        for lv in res["levels"]:
+            vol += (lv["n_pos"] + lv["n_neg"] + lv["n_conv"]) * 8.0 ** -lv["level"]
+        vol += res["leaves"].size * 8.0 ** -9
+        assert vol == 1.0
+        for level, codes in res["converged"]:
+            lo, hi = q.cell_bounds(codes, level, (-1,) * 3, (1,) * 3)
+            assert np.all(hi - lo < delta / math.sqrt(3.0))
+            mn, mx = _l1_range_over_box(lo, hi)
+            assert np.all(mn <= R) and np.all(mx >= R)
