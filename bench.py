@@ -137,6 +137,50 @@ def frusta_extra(ctx, g, dev, side=512, seed=600, tiles=(16, 16)):
     return out
 
 
+def queries_extra(ctx, g, dev):
+    """The other hierarchical queries on the 8x256 blob: empty spheres
+    (Section 4.4) for 100k uniform points (r0 = 0.5 down to 1/4096), the
+    delta-convergence tree (Procedure 3, delta = 0.02, paper arithmetic) and
+    the intersection test of the blob against a shifted copy of itself
+    (Section 4.9, depth 8)."""
+    import torch
+    import workloads as wl
+    from paper_2202_02444_amd import spk
+    out = {}
+    n = 100000
+    p = torch.from_numpy(wl.points(n, 700)).to(dev)
+    rad = torch.empty(n, device=dev)
+    lab = torch.empty(n, dtype=torch.uint8, device=dev)
+    spk.empty_spheres(ctx, g, p[:1000], rad[:1000], lab[:1000], 0.5, 1.0 / 4096)
+    for name, rig in (("rigorous", True), ("paper", False)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        spk.empty_spheres(ctx, g, p, rad, lab, 0.5, 1.0 / 4096, rigorous=rig)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        r = rad.cpu().numpy()
+        out["empty_spheres_" + name] = {"queries": n, "queries_per_s": n / dt, "answered": float((r > 0).mean()),
+                                        "median_radius": float(np.median(r))}
+    t = time.perf_counter()
+    levels, leaves = spk.build_delta_tree(ctx, g, 0.02, 10, "truncate", K_KEEP, rigorous=False)
+    torch.cuda.synchronize()
+    out["delta_tree"] = {"delta": 0.02, "seconds": time.perf_counter() - t,
+                         "frontier": [lv["n"] for lv in levels], "leaves": [lv["n_leaves"] for lv in levels]}
+    spec = wl.scale_net(1)
+    shifted = wl.MLPSpec([w.copy() for w in spec.weights], [b.copy() for b in spec.biases], act=spec.act)
+    shifted.biases[0] = (shifted.biases[0] - shifted.weights[0] @ np.array([0.3, 0.0, 0.0], np.float32)).astype(
+        np.float32)
+    g2 = spk.Net.from_spec(shifted)
+    for name, rig in (("paper", False), ("rigorous_f64", True)):
+        t = time.perf_counter()
+        r = spk.intersect(ctx, g, g2, 8, "truncate", K_KEEP, rigorous=rig, prec="f64" if rig else "f32")
+        torch.cuda.synchronize()
+        r["seconds"] = time.perf_counter() - t
+        out["intersect_" + name] = r
+    g2.close()
+    return out
+
+
 def closest_point_extra(ctx, dev, n=4096, max_level=10, n_blob=256, blob_level=6):
     """Closest point (Section 4.10) for n uniform queries, affine-fixed cells,
     on the tiny 3->32->32->1 ReLU net at level 10, and for n_blob queries on
@@ -410,7 +454,7 @@ def main():
     ap.add_argument("--boxes", type=int, default=N_BOXES)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the octree / ray extra measurements")
-    ap.add_argument("--extras", default="octree,rays,frusta,closest,batched,precision,serving",
+    ap.add_argument("--extras", default="octree,rays,frusta,queries,closest,batched,precision,serving",
                     help="comma-separated extra measurements to run")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -518,6 +562,9 @@ def main():
         if "frusta" in which:
             extra["frusta"] = frusta_extra(ctx, g, dev)
             progress("frusta done")
+        if "queries" in which:
+            extra["queries"] = queries_extra(ctx, g, dev)
+            progress("queries done")
         if "closest" in which:
             extra["closest_point"] = closest_point_extra(ctx, dev)
             progress("closest point done")

@@ -222,7 +222,7 @@ def test_rays_vs_oracle(ctx, netname, rigorous):
     both = np.isfinite(th) & np.isfinite(to)
     agree = np.isfinite(th) == np.isfinite(to)
     assert agree.mean() >= 0.98, agree.mean()
-    near = np.abs(np.where(both, th - to, 0.0)) <= 2 * delta + 1e-4
+    near = np.abs(np.where(both, th, 0.0) - np.where(both, to, 0.0)) <= 2 * delta + 1e-4
     assert near.mean() >= 0.98, near.mean()
     tau = TOL * s_net(net)
     differ = np.flatnonzero(~agree | ~near)
