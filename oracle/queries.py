@@ -11,6 +11,8 @@
 * :func:`empty_spheres` -- Section 4.4 empty-sphere radii by shrinking cubes.
 * :func:`intersect`     -- Section 4.9 intersection test of two shapes on a
   shared octree.
+* :func:`mesh_leaves`   -- Section 4.7 mesh extraction: marching cubes on the
+  dense grid of each leaf cell.
 """
 from __future__ import annotations
 
@@ -553,3 +555,106 @@ def intersect(net_f, net_g, max_level, policy="truncate", k=31, dom_lo=(-1, -1, 
         codes = np.sort(np.concatenate([(keep << np.uint64(3)) | np.uint64(o) for o in range(8)])) \
             if keep.size else np.zeros(0, dtype=np.uint64)
     raise AssertionError("unreachable")
+
+
+# ---------------------------------------------------------------------------
+# Mesh extraction in the leaf cells (Section 4.7; Appendix B dense levels)
+# ---------------------------------------------------------------------------
+
+# corner c of a cube = (c & 1, (c >> 1) & 1, (c >> 2) & 1); the 12 edges as
+# corner pairs, and the 6 faces as cyclic corner lists
+MC_EDGES = [(0, 1), (2, 3), (4, 5), (6, 7), (0, 2), (1, 3), (4, 6), (5, 7), (0, 4), (1, 5), (2, 6), (3, 7)]
+MC_FACES = [(0, 2, 6, 4), (1, 3, 7, 5), (0, 1, 5, 4), (2, 3, 7, 6), (0, 1, 3, 2), (4, 5, 7, 6)]
+
+
+def _mc_edge_index(a, b):
+    return MC_EDGES.index((min(a, b), max(a, b)))
+
+
+def mc_cube(v, p):
+    """Marching cubes in one cube from its 8 corner values v (sign test
+    v > 0, zero counts as inside) and corner positions p [8, 3].  Written
+    without a case table: each face joins its crossing edges by segments (two
+    crossings: one segment; four: the two corners whose sign differs from the
+    face's mean are each cut off by the segment between their two edges), the
+    segments close into loops over the crossing edges, and each loop, walked
+    from its lowest edge toward that edge's lower-numbered neighbour, is
+    triangulated as a fan.  Edge points interpolate f linearly.  Returns a
+    list of triangles, each [3, 3]."""
+    s = [bool(x > 0.0) for x in v]
+    cross = [s[a] != s[b] for a, b in MC_EDGES]
+    if not any(cross):
+        return []
+    pt = {}
+    for e, (a, b) in enumerate(MC_EDGES):
+        if cross[e]:
+            t = v[a] / (v[a] - v[b])
+            pt[e] = p[a] + t * (p[b] - p[a])
+    nb = {e: [] for e in pt}
+    for q in MC_FACES:
+        edges = [_mc_edge_index(q[i], q[(i + 1) % 4]) for i in range(4)]
+        ce = [e for e in edges if cross[e]]
+        if len(ce) == 2:
+            segs = [(ce[0], ce[1])]
+        elif len(ce) == 4:
+            center = (v[q[0]] + v[q[1]] + v[q[2]] + v[q[3]]) / 4.0 > 0.0
+            segs = [(edges[(i - 1) % 4], edges[i]) for i in range(4) if s[q[i]] != center]
+        else:
+            segs = []
+        for a, b in segs:
+            nb[a].append(b)
+            nb[b].append(a)
+    tris = []
+    used = set()
+    for e0 in sorted(pt):
+        if e0 in used:
+            continue
+        loop = [e0]
+        used.add(e0)
+        prev, cur = e0, min(nb[e0])
+        while cur != e0:
+            loop.append(cur)
+            used.add(cur)
+            a, b = nb[cur]
+            prev, cur = cur, (b if a == prev else a)
+        for i in range(1, len(loop) - 1):
+            tris.append(np.stack([pt[loop[0]], pt[loop[i]], pt[loop[i + 1]]]))
+    return tris
+
+
+def mesh_leaves(net, leaves, level, dense_levels=3, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1)):
+    """Triangles of the level set inside the given leaf cells (Morton codes at
+    `level`): each leaf is sampled on the grid of dense_levels further
+    subdivisions (Appendix B: dense evaluation of the lowest levels) and
+    every grid cube is meshed by :func:`mc_cube`.  Grid points are
+    dom_lo + g h with g the global index on the finest grid, so neighbouring
+    leaves share their face samples.  Returns ([m, 3, 3] triangles, [m] index
+    of the leaf, [m] index of the cube in the leaf, x-fastest)."""
+    dom_lo = np.asarray(dom_lo, dtype=np.float64)
+    dom_hi = np.asarray(dom_hi, dtype=np.float64)
+    R = 1 << dense_levels
+    h = (dom_hi - dom_lo) / float(1 << (level + dense_levels))
+    ix, iy, iz = morton_decode(np.asarray(leaves, dtype=np.uint64), level)
+    g = np.arange(R + 1)
+    out, owner, cube = [], [], []
+    for j in range(len(leaves)):
+        base = np.array([ix[j], iy[j], iz[j]], dtype=np.int64) * R
+        G = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)   # (i, j, k) x slowest
+        P = dom_lo + (base + G) * h
+        F = mlp.forward(net, P).reshape(R + 1, R + 1, R + 1)
+        P = P.reshape(R + 1, R + 1, R + 1, 3)
+        for kz in range(R):
+            for ky in range(R):
+                for kx in range(R):
+                    cs = [(kx + (c & 1), ky + ((c >> 1) & 1), kz + ((c >> 2) & 1)) for c in range(8)]
+                    v = [F[a, b, cc] for a, b, cc in cs]
+                    if all(x > 0 for x in v) or all(x <= 0 for x in v):
+                        continue
+                    p = np.stack([P[a, b, cc] for a, b, cc in cs])
+                    for t in mc_cube(v, p):
+                        out.append(t)
+                        owner.append(j)
+                        cube.append(kx + R * (ky + R * kz))
+    if not out:
+        return np.zeros((0, 3, 3)), np.zeros(0, np.int64), np.zeros(0, np.int64)
+    return np.stack(out), np.array(owner), np.array(cube)

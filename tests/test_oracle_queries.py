@@ -406,3 +406,63 @@ def test_delta_tree_octahedron():
             assert np.all(hi - lo < delta / math.sqrt(3.0))
             mn, mx = _l1_range_over_box(lo, hi)
             assert np.all(mn <= R) and np.all(mx >= R)
+
+
+def _mesh_topology(tris):
+    """(V, E, F, edges used by other than two triangles) of a triangle soup
+    whose shared vertices are bitwise equal."""
+    vid = {}
+    faces = []
+    for t in tris:
+        ids = []
+        for v in t:
+            key = tuple(float(x) for x in v)
+            ids.append(vid.setdefault(key, len(vid)))
+        faces.append(ids)
+    from collections import Counter
+    ec = Counter()
+    for a, b, c in faces:
+        for u, w in ((a, b), (b, c), (c, a)):
+            ec[(min(u, w), max(u, w))] += 1
+    bad = sum(1 for k, n in ec.items() if n != 2)
+    return len(vid), len(ec), len(faces), bad
+
+
+def test_mc_cube_every_sign_pattern():
+    """All 256 corner sign patterns of one cube: the triangles' vertices are
+    exactly the crossing edges' interpolated points, every crossing edge is
+    used, and the loops cut the cube consistently: the number of triangles is
+    (crossing edges) - 2 (loops)."""
+    rng = np.random.default_rng(5)
+    p = np.array([[c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], dtype=np.float64)
+    for pattern in range(256):
+        v = [(rng.uniform(0.1, 1.0) if (pattern >> c) & 1 else -rng.uniform(0.1, 1.0)) for c in range(8)]
+        tris = q.mc_cube(v, p)
+        cross = [(a, b) for a, b in q.MC_EDGES if (v[a] > 0) != (v[b] > 0)]
+        pts = {tuple(p[a] + v[a] / (v[a] - v[b]) * (p[b] - p[a])) for a, b in cross}
+        used = {tuple(x) for t in tris for x in t}
+        assert used == pts, pattern
+        if cross:
+            V, E, F, bad = _mesh_topology(tris)
+            # each loop of m points is a fan of m - 2 triangles
+            assert V == len(cross) and (V - F) % 2 == 0 and (V - F) // 2 >= 1, pattern
+            # the loops are closed polygons: their m sides are the edges used
+            # once (the segments on the cube's faces), the fan diagonals twice
+            assert bad == len(cross), pattern
+
+
+def test_mesh_octahedron_is_closed_and_exact():
+    """Leaves of the exact octahedron's octree at level 2, meshed with 3 dense
+    levels (a 32^3 grid whose lines include the coordinate planes, so f is
+    linear on every grid edge): every vertex lies exactly on |x|_1 = R, every
+    mesh edge is shared by exactly two triangles, and the Euler
+    characteristic is 2 (a sphere)."""
+    R = 0.55
+    net = wl.octahedron_mlp(R)
+    res = q.octree_build(net, 2, "fixed", 0)
+    tris, owner, cube = q.mesh_leaves(net, res["leaves"], 2, 3)
+    assert tris.shape[0] > 100
+    assert np.allclose(np.abs(tris).sum(axis=2), R, atol=1e-12)
+    V, E, F, bad = _mesh_topology(tris)
+    assert bad == 0
+    assert V - E + F == 2
