@@ -140,8 +140,9 @@ def frusta_extra(ctx, g, dev, side=512, seed=600, tiles=(16, 16)):
 def queries_extra(ctx, g, dev):
     """The other hierarchical queries on the 8x256 blob: empty spheres
     (Section 4.4) for 100k uniform points (r0 = 0.5 down to 1/4096), the
-    delta-convergence tree (Procedure 3, delta = 0.02, paper arithmetic) and
-    the intersection test of the blob against a shifted copy of itself
+    delta-convergence tree (Procedure 3, delta = 0.02, paper arithmetic),
+    mesh extraction in the level-6 leaves with 3 dense levels (Section 4.7)
+    and the intersection test of the blob against a shifted copy of itself
     (Section 4.9, depth 8)."""
     import torch
     import workloads as wl
@@ -166,6 +167,18 @@ def queries_extra(ctx, g, dev):
     torch.cuda.synchronize()
     out["delta_tree"] = {"delta": 0.02, "seconds": time.perf_counter() - t,
                          "frontier": [lv["n"] for lv in levels], "leaves": [lv["n_leaves"] for lv in levels]}
+    # mesh extraction: the level-6 leaves of the paper-arithmetic octree, 3
+    # dense levels (a 512^3 grid inside the leaves)
+    levels6, leaves6 = spk.build_octree(ctx, g, 6, "truncate", K_KEEP, rigorous=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tris = spk.mesh_leaves(ctx, g, leaves6, 6, 3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    out["mesh"] = {"leaf_level": 6, "dense_levels": 3, "leaves": int(leaves6.shape[0]),
+                   "grid_points": int(leaves6.shape[0]) * 729, "triangles": int(tris.shape[0]), "seconds": dt,
+                   "grid_points_per_s": int(leaves6.shape[0]) * 729 / dt}
+    del tris
     spec = wl.scale_net(1)
     shifted = wl.MLPSpec([w.copy() for w in spec.weights], [b.copy() for b in spec.biases], act=spec.act)
     shifted.biases[0] = (shifted.biases[0] - shifted.weights[0] @ np.array([0.3, 0.0, 0.0], np.float32)).astype(

@@ -284,6 +284,29 @@ typedef struct {
 } spk_ray_params;
 
 /*
+ * spk_mesh_leaves (Section 4.7): triangles of the level set inside leaf cells
+ * (Morton codes at `level` in tree's domain, e.g. the leaves of the last
+ * frontier round).  Each leaf is sampled on the grid of dense_levels (0..4)
+ * further subdivisions (Appendix B evaluates the lowest levels densely; its
+ * meshes use 3): points dom_lo + g h with g the index on the finest grid, so
+ * neighbouring leaves share their face samples exactly, and every grid cube
+ * is meshed by marching cubes without a case table (each face joins its
+ * crossing edges; a face with four crossings cuts off the corners whose sign
+ * differs from the mean of its four values; the loops are triangulated as
+ * fans; edge points interpolate f linearly; f > 0 is outside).
+ *   tris    dev float [cap_tris][3][3]; tri_src dev int32 [cap_tris][2]
+ *           nullable: the leaf's index and the cube's index in it
+ *           (x fastest).  Output order is unspecified.
+ *   n_tris  host: the number of triangles; SPK_E_NOSPC when it exceeds
+ *           cap_tris (the first cap_tris are written).
+ * Synchronous; about 12 bytes per grid point of a chunk of leaves (at most
+ * 256 MiB) stream-ordered within the context's workspace limit.
+ */
+spk_status spk_mesh_leaves(spk_ctx* ctx, const spk_net* net, const spk_tree_params* tree, int32_t level,
+                           int32_t dense_levels, int64_t n_leaves, const uint64_t* leaves, float* tris,
+                           int32_t* tri_src, int64_t cap_tris, int64_t* n_tris);
+
+/*
  * spk_intersect (Section 4.9): whether the solids {f < 0} and {g < 0} of two
  * networks overlap inside the tree domain, by octree rounds (arity 8) that
  * bound both networks on every frontier cell: a cell with either function

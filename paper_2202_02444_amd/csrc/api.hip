@@ -886,6 +886,60 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
   return check_hip(hipStreamSynchronize(ctx->stream));
 }
 
+// Mesh extraction in leaf cells (Section 4.7); kernels in mesh.hip.
+spk_status spk_mesh_leaves(spk_ctx* ctx, const spk_net* net, const spk_tree_params* tree, int32_t level,
+                           int32_t dense_levels, int64_t n_leaves, const uint64_t* leaves, float* tris,
+                           int32_t* tri_src, int64_t cap_tris, int64_t* n_tris) {
+  if (ctx == nullptr || net == nullptr || tree == nullptr || n_tris == nullptr) return SPK_E_INVAL;
+  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
+  for (int d = 0; d < 3; ++d)
+    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
+      return SPK_E_INVAL;
+  if (level < 0 || dense_levels < 0 || dense_levels > 4 || level + dense_levels > 20) return SPK_E_INVAL;
+  if (n_leaves < 0 || n_leaves > (int64_t)0x7fffffff || cap_tris < 0) return SPK_E_INVAL;
+  if ((n_leaves > 0 && leaves == nullptr) || (cap_tris > 0 && tris == nullptr)) return SPK_E_INVAL;
+  *n_tris = 0;
+  if (n_leaves == 0) return SPK_OK;
+  const int R = 1 << dense_levels, NV = (R + 1) * (R + 1) * (R + 1);
+  void *pts = nullptr, *vals = nullptr, *cnt = nullptr;
+  size_t c_pts = 0, c_vals = 0, c_cnt = 0;
+  CallBuffers B;
+  B.limit = ctx->workspace_limit;
+  B.stream = ctx->stream;
+  B.peak = &ctx->ws_peak;
+  // chunks of leaves whose grid points take at most 256 MiB
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_leaves, ((int64_t)256 << 20) / ((int64_t)NV * 16)));
+  spk_status st = B.ensure(&pts, c_pts, (size_t)chunk * NV * 12);
+  if (st == SPK_OK) st = B.ensure(&vals, c_vals, (size_t)chunk * NV * 4);
+  if (st == SPK_OK) st = B.ensure(&cnt, c_cnt, 256);
+  if (st != SPK_OK) return st;
+  if (hipMemsetAsync(cnt, 0, 8, ctx->stream) != hipSuccess) return SPK_E_DEVICE;
+  MeshJob M = {};
+  M.leaves = leaves;
+  M.level = level;
+  M.dense = dense_levels;
+  for (int d = 0; d < 3; ++d) {
+    M.dom_lo[d] = tree->dom_lo[d];
+    M.h[d] = (float)(((double)tree->dom_hi[d] - (double)tree->dom_lo[d]) / (double)(1u << (level + dense_levels)));
+  }
+  M.tris = tris;
+  M.src = tri_src;
+  M.cap = cap_tris;
+  M.count = (unsigned long long*)cnt;
+  for (int64_t l0 = 0; l0 < n_leaves; l0 += chunk) {
+    const int64_t nl = std::min(chunk, n_leaves - l0);
+    st = launch_mesh_chunk(net, M, l0, nl, (float*)pts, (float*)vals, ctx->stream, ctx->num_cus);
+    if (st != SPK_OK) return st;
+  }
+  unsigned long long total = 0ull;
+  if (hipMemcpyAsync(&total, cnt, sizeof(total), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return SPK_E_DEVICE;
+  *n_tris = (int64_t)total;
+  net_mark_use(net, ctx->stream);
+  return (int64_t)total > cap_tris ? SPK_E_NOSPC : SPK_OK;
+}
+
 // Intersection of two shapes (Section 4.9); the combine kernel is in
 // intersect.hip.
 spk_status spk_intersect(spk_ctx* ctx, const spk_net* net_f, const spk_net* net_g, const spk_bound_opts* opts,

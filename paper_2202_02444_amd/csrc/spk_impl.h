@@ -165,6 +165,18 @@ struct CpDive {
   float* point;              // [n][3] candidates
 };
 
+// Mesh extraction in leaf cells (mesh.hip).
+struct MeshJob {
+  const uint64_t* leaves;    // [n] Morton codes at `level`
+  int32_t level, dense;      // leaf level, dense levels below it
+  float dom_lo[3];
+  float h[3];                // finest grid spacing
+  float* tris;               // [cap][3][3]
+  int32_t* src;              // [cap][2] nullable: leaf index, cube index
+  int64_t cap;
+  unsigned long long* count;
+};
+
 // One round of the two-shape intersection test (intersect.hip).
 struct IxRound {
   int64_t n;
@@ -316,6 +328,8 @@ hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix,
 spk_status launch_converge(const spk_net* net, uint8_t* labels, const uint64_t* cells, int64_t n, int level,
                            const float (&dom_lo)[3], const float (&dom_hi)[3], float* fpts, float* fvals,
                            hipStream_t stream, int num_cus);
+spk_status launch_mesh_chunk(const spk_net* net, const MeshJob& M, int64_t l0, int64_t nl, float* pts, float* vals,
+                             hipStream_t stream, int num_cus);
 spk_status launch_ix_round(const IxRound& X, hipStream_t stream, int num_cus);
 spk_status launch_es_init(const EsRound& E, hipStream_t stream);
 spk_status launch_es_boxes(const EsRound& E, int64_t m, hipStream_t stream);

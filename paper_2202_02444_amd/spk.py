@@ -24,7 +24,7 @@ UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
            "spk_subdivide_frontier", "spk_subdivide_frontier_noalloc", "spk_cast_rays", "spk_cast_frusta",
-           "spk_empty_spheres", "spk_intersect",
+           "spk_empty_spheres", "spk_intersect", "spk_mesh_leaves",
            "spk_eval_points", "spk_closest_point",
            "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
            "spk_batch_destroy", "spk_server_create", "spk_server_submit", "spk_server_poll",
@@ -141,6 +141,8 @@ def lib():
         L.spk_subdivide_frontier_noalloc.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
+        L.spk_mesh_leaves.argtypes = [vp, vp, ctypes.POINTER(TreeParams), i32, i32, i64, vp, vp, vp, i64,
+                                      ctypes.POINTER(i64)]
         L.spk_intersect.argtypes = [vp, vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams),
                                     ctypes.POINTER(IntersectResult)]
         L.spk_empty_spheres.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), i64, vp, ctypes.c_float,
@@ -356,6 +358,33 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
                              _ptr(direction, torch.float32, (n, 3), "direction"),
                              _ptr(t_hit, torch.float32, (n,), "t_hit"), _ptr(iters, torch.int32, (n,), "iters"))
     _check(st, "spk_cast_rays")
+
+
+def mesh_leaves(ctx, net, leaves, level, dense_levels=3, cap=None, dom_lo=(-1.0, -1.0, -1.0),
+                dom_hi=(1.0, 1.0, 1.0), with_src=False):
+    """spk_mesh_leaves: triangles [m, 3, 3] (GPU tensor) of the level set in
+    the leaf cells (int64 Morton codes at `level`); with_src also returns the
+    [m, 2] (leaf index, cube index) of each triangle.  The capacity grows and
+    the call repeats once if the first guess was too small."""
+    import torch
+    dev = torch.device("cuda")
+    n = leaves.shape[0]
+    tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(level), 8)
+    cap = int(cap if cap is not None else max(1024, 4 * n * (1 << (2 * dense_levels))))
+    for _ in range(2):
+        tris = torch.empty((max(cap, 1), 3, 3), device=dev)
+        src = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=dev) if with_src else None
+        m = ctypes.c_int64()
+        st = lib().spk_mesh_leaves(ctx.handle, net.handle, ctypes.byref(tp), int(level), int(dense_levels), n,
+                                   _ptr(leaves, torch.int64, (n,), "leaves"), _ptr(tris, torch.float32, None, "tris"),
+                                   _ptr(src, torch.int32, None, "tri_src"), cap, ctypes.byref(m))
+        if st == E_NOSPC:
+            cap = int(m.value)
+            continue
+        _check(st, "spk_mesh_leaves")
+        tris = tris[:m.value]
+        return (tris, src[:m.value]) if with_src else tris
+    raise SpkError(E_NOSPC, "spk_mesh_leaves")
 
 
 def intersect(ctx, net_f, net_g, max_level=8, policy="truncate", k=31, rigorous=True, prec="f32",

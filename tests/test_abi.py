@@ -131,6 +131,22 @@ def test_tree_and_ray_validation():
     assert spk.ray_params(rigorous=False).flags == spk.FLAG_NO_ROUNDING_BOUND and spk.ray_params().flags == 0
 
 
+def test_mesh_validation():
+    L = spk.lib()
+    tp = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 4, 8)
+    m = ctypes.c_int64()
+    call = lambda t, lvl, dense, n, lv, tris, cap, out: L.spk_mesh_leaves(FAKE, FAKE, ctypes.byref(t), lvl, dense, n,
+                                                                         lv, tris, None, cap, out)
+    assert call(tp, 3, 3, 4, FAKE, FAKE, 8, None) == spk.E_INVAL                   # no count output
+    assert call(tp, 3, 5, 4, FAKE, FAKE, 8, ctypes.byref(m)) == spk.E_INVAL        # too many dense levels
+    assert call(tp, 18, 3, 4, FAKE, FAKE, 8, ctypes.byref(m)) == spk.E_INVAL       # finer than level 20
+    assert call(tp, 3, 3, 4, None, FAKE, 8, ctypes.byref(m)) == spk.E_INVAL        # no leaves
+    assert call(tp, 3, 3, 4, FAKE, None, 8, ctypes.byref(m)) == spk.E_INVAL        # capacity without a buffer
+    assert call(tp, 3, 3, 0, None, None, 0, ctypes.byref(m)) == spk.OK and m.value == 0
+    kd = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 4, 2)
+    assert call(kd, 3, 3, 4, FAKE, FAKE, 8, ctypes.byref(m)) == spk.E_UNSUPPORTED
+
+
 def test_delta_tree_validation():
     L = spk.lib()
     o = spk.opts("truncate", 31)
