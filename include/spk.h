@@ -216,14 +216,18 @@ spk_status spk_classify_boxes(spk_ctx* ctx, const spk_net* net, const spk_bound_
  * (spk_subdivide_frontier only; the other calls require 0): at a level whose
  * cells' widest side is below delta / sqrt(3), an UNKNOWN cell whose six face
  * centers show both signs of f (FP32 evaluation) is within delta of the level
- * set and final; it goes to `leaves` instead of splitting. */
+ * set and final; it goes to `leaves` instead of splitting.
+ * band r > 0 (spk_subdivide_frontier only; not with delta) classifies
+ * against the band |f| <= r instead of the level set (Section 4.6): a cell is
+ * POSITIVE when f > r on it and NEGATIVE when f < -r, so the UNKNOWN cells
+ * cover every point with |f| <= r. */
 typedef struct {
   float dom_lo[3];
   float dom_hi[3];
   int32_t max_level;   /* 0 <= max_level <= 20                                   */
   int32_t arity;       /* 8 (octree); other values give SPK_E_UNSUPPORTED        */
   float delta;         /* 0: fixed depth; > 0: convergence test (finite)         */
-  int32_t reserved;
+  float band;          /* 0: the level set; > 0: the band |f| <= band (finite)   */
 } spk_tree_params;
 
 /*
@@ -282,6 +286,26 @@ typedef struct {
                            root on the segment; SPK_FLAG_NO_ROUNDING_BOUND: the
                            paper's arithmetic with the tolerance margin          */
 } spk_ray_params;
+
+/*
+ * spk_sample_leaves (surface sampling, Section 4.6; bulk properties,
+ * Section 4.8): n_samples uniform points in the union of n_leaves leaf cells
+ * of one level (e.g. the UNKNOWN leaves of a tree built with
+ * spk_tree_params.band = r, which cover every point with |f| <= r).  Sample
+ * i takes outputs 4i .. 4i+3 of the splitmix64 generator seeded with `seed`
+ * (z = seed + (k + 1) 0x9e3779b97f4a7c15; z = (z ^ z >> 30) 0xbf58476d1ce4e5b9;
+ * z = (z ^ z >> 27) 0x94d049bb133111eb; z ^ z >> 31): leaf = output 4i mod
+ * n_leaves, offsets u_d = (output 4i+1+d >> 40) 2^-24, point = lo + u (hi - lo)
+ * (FP32).  Samples with |f| < band (band = +inf: all) are written, in
+ * unspecified order, to points dev [cap][3] and f dev [cap] (nullable).
+ *   n_accepted host: accepted samples (SPK_E_NOSPC when above cap; the first
+ *              cap are written); n_below host nullable: accepted with f < 0.
+ * Synchronous; 16 bytes per sample of a chunk of at most 2^24 samples,
+ * stream-ordered within the context's workspace limit.
+ */
+spk_status spk_sample_leaves(spk_ctx* ctx, const spk_net* net, const spk_tree_params* tree, int32_t level,
+                             int64_t n_leaves, const uint64_t* leaves, int64_t n_samples, uint64_t seed, float band,
+                             float* points, float* f, int64_t cap, int64_t* n_accepted, int64_t* n_below);
 
 /*
  * spk_mesh_leaves (Section 4.7): triangles of the level set inside leaf cells

@@ -13,6 +13,8 @@
   shared octree.
 * :func:`mesh_leaves`   -- Section 4.7 mesh extraction: marching cubes on the
   dense grid of each leaf cell.
+* :func:`sample_leaves`, :func:`bulk_volume` -- Sections 4.6 and 4.8: uniform
+  samples in leaf cells (surface band sampling) and the solid's volume.
 """
 from __future__ import annotations
 
@@ -115,7 +117,7 @@ def kd_bounds(code, depth, dom_lo, dom_hi):
 
 
 def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1),
-                 arity=8, keep_leaf_lists=False, max_cells=None, delta=None):
+                 arity=8, keep_leaf_lists=False, max_cells=None, delta=None, band=0.0):
     """Fixed-depth BuildSpatialTree in parallel rounds.
 
     Each round classifies every cell of the current level: POSITIVE and
@@ -128,7 +130,9 @@ def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), d
     With ``delta`` (octree only) the convergence test of Procedure 3 applies:
     at a level whose cells' widest side is below delta / sqrt(3), an UNKNOWN
     cell whose six face centers show both signs of f is final (within delta of
-    the level set); ``converged`` then lists (level, sorted codes).
+    the level set); ``converged`` then lists (level, sorted codes).  With
+    ``band`` r > 0 cells are classified against the band |f| <= r (Section
+    4.6): POSITIVE when f > r, NEGATIVE when f < -r.
     """
     codes = np.zeros(1, dtype=np.uint64)
     levels = []
@@ -142,7 +146,7 @@ def octree_build(net, max_level, policy="truncate", k=31, dom_lo=(-1, -1, -1), d
             lo, hi = kd_bounds(codes, level, dom_lo, dom_hi)
         if codes.size:
             _, _, ly, hy = mlp.bound_boxes(net, lo, hi, policy, k)
-            lab = classify(ly, hy)
+            lab = classify(ly - band, hy + band)
         else:
             lab = np.zeros(0, dtype=np.uint8)
         unk = codes[lab == UNKNOWN]
@@ -658,3 +662,56 @@ def mesh_leaves(net, leaves, level, dense_levels=3, dom_lo=(-1, -1, -1), dom_hi=
     if not out:
         return np.zeros((0, 3, 3)), np.zeros(0, np.int64), np.zeros(0, np.int64)
     return np.stack(out), np.array(owner), np.array(cube)
+
+
+# ---------------------------------------------------------------------------
+# Sampling in leaf cells: surface sampling (Section 4.6) and bulk properties
+# (Section 4.8)
+# ---------------------------------------------------------------------------
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed, k):
+    """The k-th output (k = 0, 1, ...) of the splitmix64 generator (Steele,
+    Lea and Flood, 2014) seeded with `seed`, for an array k (Python integers,
+    exact 64-bit wrap-around)."""
+    out = []
+    for kk in np.asarray(k, dtype=np.uint64).ravel().tolist():
+        z = (int(seed) + (int(kk) + 1) * 0x9e3779b97f4a7c15) & _M64
+        z = ((z ^ (z >> 30)) * 0xbf58476d1ce4e5b9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94d049bb133111eb) & _M64
+        out.append(z ^ (z >> 31))
+    return np.array(out, dtype=np.uint64).reshape(np.shape(k))
+
+
+def sample_leaves(net, leaves, level, n_samples, seed, band=math.inf, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1)):
+    """Uniform samples in the union of equal-size leaf cells: sample i takes
+    outputs 4i .. 4i+3 of splitmix64(seed): the leaf (first output modulo the
+    leaf count) and 24-bit offsets in [0, 1) per axis.  Returns (points
+    [n, 3], f [n], accepted mask |f| < band)."""
+    leaves = np.asarray(leaves, dtype=np.uint64)
+    i = np.arange(n_samples, dtype=np.uint64)
+    leaf = (splitmix64(seed, 4 * i) % np.uint64(leaves.size)).astype(np.int64)
+    lo, hi = cell_bounds(leaves[leaf], level, dom_lo, dom_hi)
+    u = np.stack([(splitmix64(seed, 4 * i + np.uint64(1 + d)) >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+                  for d in range(3)], axis=1)
+    pts = lo + u * (hi - lo)
+    f = mlp.forward(net, pts)
+    return pts, f, np.abs(f) < band
+
+
+def bulk_volume(net, max_level, n_samples, seed, policy="truncate", k=31, dom_lo=(-1, -1, -1), dom_hi=(1, 1, 1)):
+    """Volume of the solid {f < 0} (Section 4.8): the NEGATIVE cells of the
+    fixed-depth tree count in full, the UNKNOWN leaves by the fraction of
+    uniform samples in them with f < 0.  Returns (estimate, lower bound,
+    upper bound): the solid holds every NEGATIVE cell and lies within the
+    NEGATIVE cells and the leaves."""
+    res = octree_build(net, max_level, policy, k, dom_lo, dom_hi)
+    dom = float(np.prod(np.asarray(dom_hi, dtype=np.float64) - np.asarray(dom_lo, dtype=np.float64)))
+    v_neg = sum(lv["n_neg"] * dom / 8.0 ** lv["level"] for lv in res["levels"])
+    v_leaf = res["leaves"].size * dom / 8.0 ** max_level
+    if res["leaves"].size == 0:
+        return v_neg, v_neg, v_neg
+    _, f, _ = sample_leaves(net, res["leaves"], max_level, n_samples, seed, math.inf, dom_lo, dom_hi)
+    return v_neg + v_leaf * float(np.mean(f < 0.0)), v_neg, v_neg + v_leaf

@@ -551,6 +551,7 @@ static spk_status subdivide_round(spk_ctx* ctx, const spk_net* net, const spk_bo
   }
   job.label = labels;
   job.nonfinite = (unsigned long long*)ctx->status;
+  job.band = tree->band;
   if (n > 0) {
     spk_status st = launch_bound(net, job, ctx->stream, ctx->num_cus);
     if (st != SPK_OK) return st;
@@ -577,6 +578,7 @@ static spk_status check_subdivide_args(spk_ctx* ctx, const spk_net* net, const s
     if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
       return SPK_E_INVAL;
   if (!(tree->delta >= 0.0f) || !isfinite(tree->delta)) return SPK_E_INVAL;
+  if (!(tree->band >= 0.0f) || !isfinite(tree->band) || (tree->band > 0.0f && tree->delta > 0.0f)) return SPK_E_INVAL;
   if (n < 0 || cap_children < 0 || cap_leaves < 0) return SPK_E_INVAL;
   if (n > 0 && cells == nullptr) return SPK_E_INVAL;
   if ((cap_children > 0 && children == nullptr) || (cap_leaves > 0 && leaves == nullptr)) return SPK_E_INVAL;
@@ -856,7 +858,7 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
   spk_status st = valid_opts(opts);
   if (st != SPK_OK) return st;
   if (tree->arity != 8) return SPK_E_UNSUPPORTED;
-  if (tree->max_level < 0 || tree->max_level > 20 || tree->delta != 0.0f) return SPK_E_INVAL;
+  if (tree->max_level < 0 || tree->max_level > 20 || tree->delta != 0.0f || tree->band != 0.0f) return SPK_E_INVAL;
   for (int d = 0; d < 3; ++d)
     if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
       return SPK_E_INVAL;
@@ -884,6 +886,62 @@ spk_status spk_closest_point(spk_ctx* ctx, const spk_net* net, const spk_bound_o
     c0 += cn;
   }
   return check_hip(hipStreamSynchronize(ctx->stream));
+}
+
+// Sampling in leaf cells (Sections 4.6, 4.8); kernels in samples.hip.
+spk_status spk_sample_leaves(spk_ctx* ctx, const spk_net* net, const spk_tree_params* tree, int32_t level,
+                             int64_t n_leaves, const uint64_t* leaves, int64_t n_samples, uint64_t seed, float band,
+                             float* points, float* f, int64_t cap, int64_t* n_accepted, int64_t* n_below) {
+  if (ctx == nullptr || net == nullptr || tree == nullptr || n_accepted == nullptr) return SPK_E_INVAL;
+  if (tree->arity != 8) return SPK_E_UNSUPPORTED;
+  for (int d = 0; d < 3; ++d)
+    if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
+      return SPK_E_INVAL;
+  if (level < 0 || level > 20 || n_leaves < 0 || n_samples < 0 || cap < 0 || !(band > 0.0f)) return SPK_E_INVAL;
+  if ((n_leaves > 0 && leaves == nullptr) || (cap > 0 && points == nullptr)) return SPK_E_INVAL;
+  if (n_samples > 0 && n_leaves == 0) return SPK_E_INVAL;
+  *n_accepted = 0;
+  if (n_below) *n_below = 0;
+  if (n_samples == 0) return SPK_OK;
+  void *pts = nullptr, *vals = nullptr, *cnt = nullptr;
+  size_t c_pts = 0, c_vals = 0, c_cnt = 0;
+  CallBuffers B;
+  B.limit = ctx->workspace_limit;
+  B.stream = ctx->stream;
+  B.peak = &ctx->ws_peak;
+  const int64_t chunk = std::min<int64_t>(n_samples, (int64_t)1 << 24);
+  spk_status st = B.ensure(&pts, c_pts, (size_t)chunk * 12);
+  if (st == SPK_OK) st = B.ensure(&vals, c_vals, (size_t)chunk * 4);
+  if (st == SPK_OK) st = B.ensure(&cnt, c_cnt, 256);
+  if (st != SPK_OK) return st;
+  if (hipMemsetAsync(cnt, 0, 16, ctx->stream) != hipSuccess) return SPK_E_DEVICE;
+  SampleJob J = {};
+  J.leaves = leaves;
+  J.n_leaves = n_leaves;
+  J.level = level;
+  for (int d = 0; d < 3; ++d) {
+    J.dom_lo[d] = tree->dom_lo[d];
+    J.dom_hi[d] = tree->dom_hi[d];
+  }
+  J.seed = seed;
+  J.band = band;
+  J.points = points;
+  J.f = f;
+  J.cap = cap;
+  J.counts = (unsigned long long*)cnt;
+  for (int64_t i0 = 0; i0 < n_samples; i0 += chunk) {
+    st = launch_sample_chunk(net, J, i0, std::min(chunk, n_samples - i0), (float*)pts, (float*)vals, ctx->stream,
+                             ctx->num_cus);
+    if (st != SPK_OK) return st;
+  }
+  unsigned long long c[2] = {0ull, 0ull};
+  if (hipMemcpyAsync(c, cnt, sizeof(c), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return SPK_E_DEVICE;
+  *n_accepted = (int64_t)c[0];
+  if (n_below) *n_below = (int64_t)c[1];
+  net_mark_use(net, ctx->stream);
+  return (int64_t)c[0] > cap ? SPK_E_NOSPC : SPK_OK;
 }
 
 // Mesh extraction in leaf cells (Section 4.7); kernels in mesh.hip.
@@ -948,7 +1006,7 @@ spk_status spk_intersect(spk_ctx* ctx, const spk_net* net_f, const spk_net* net_
   spk_status st = valid_opts(opts);
   if (st != SPK_OK) return st;
   if (tree->arity != 8) return SPK_E_UNSUPPORTED;
-  if (tree->max_level < 0 || tree->max_level > 20 || tree->delta != 0.0f) return SPK_E_INVAL;
+  if (tree->max_level < 0 || tree->max_level > 20 || tree->delta != 0.0f || tree->band != 0.0f) return SPK_E_INVAL;
   for (int d = 0; d < 3; ++d)
     if (!(tree->dom_lo[d] < tree->dom_hi[d]) || !isfinite(tree->dom_lo[d]) || !isfinite(tree->dom_hi[d]))
       return SPK_E_INVAL;

@@ -164,7 +164,8 @@ spk_status valid_item(const spk_batch_item& it) {
   }
   const spk_tree_params& t = it.tree;
   if (t.arity != 8) return SPK_E_UNSUPPORTED;
-  if (t.max_level < 0 || t.max_level > 20 || it.level < 0 || it.level > t.max_level || t.delta != 0.0f)
+  if (t.max_level < 0 || t.max_level > 20 || it.level < 0 || it.level > t.max_level || t.delta != 0.0f ||
+      t.band != 0.0f)
     return SPK_E_INVAL;
   for (int d = 0; d < 3; ++d)
     if (!(t.dom_lo[d] < t.dom_hi[d]) || !isfinite(t.dom_lo[d]) || !isfinite(t.dom_hi[d])) return SPK_E_INVAL;

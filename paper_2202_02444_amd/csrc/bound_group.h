@@ -130,7 +130,10 @@ __device__ __forceinline__ void bound_group(const NetDev& net, const BoundJob& j
   const OutVals o = output_layer<S, 0>(net, xc, y, yinf, u, lane, pass, rig);
   BoxResult r;
   enclose(o, job.rigorous != 0, r.lo, r.hi);
-  r.label = (r.lo > 0.0f) ? (uint8_t)SPK_POSITIVE : (r.hi < 0.0f) ? (uint8_t)SPK_NEGATIVE : (uint8_t)SPK_UNKNOWN;
+  // band r >= 0 (surface sampling, Section 4.6): POSITIVE means f > r on the
+  // box, NEGATIVE f < -r (r = 0: Procedure 1)
+  r.label = (r.lo > job.band) ? (uint8_t)SPK_POSITIVE : (r.hi < -job.band) ? (uint8_t)SPK_NEGATIVE
+                                                                            : (uint8_t)SPK_UNKNOWN;
   r.center = (float)o.y0;
   r.radius = o.r;
   r.err = job.rigorous ? o.err : round_up_f(tolerance_margin(o));

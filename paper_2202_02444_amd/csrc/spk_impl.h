@@ -72,6 +72,7 @@ struct BoundJob {
   float* err;
   int16_t* slot_src;
   unsigned long long* nonfinite;   // device status: boxes with non-finite inputs (nullable)
+  float band;         // classification threshold r >= 0: POSITIVE lo > r, NEGATIVE hi < -r
 };
 
 // FP32 bounds of the octree cell with Morton code `code` at `level` (bit b of
@@ -163,6 +164,21 @@ struct CpDive {
   const float* fvals;        // [48n] f at the face centers
   unsigned* best;            // [n] distance bounds (float bits)
   float* point;              // [n][3] candidates
+};
+
+// Sampling in leaf cells (samples.hip).
+struct SampleJob {
+  const uint64_t* leaves;
+  int64_t n_leaves;
+  int32_t level;
+  int32_t pad;
+  float dom_lo[3], dom_hi[3];
+  uint64_t seed;
+  float band;                // accept |f| < band
+  float* points;             // [cap][3] accepted points
+  float* f;                  // [cap] nullable
+  int64_t cap;
+  unsigned long long* counts;   // [0] accepted, [1] accepted with f < 0
 };
 
 // Mesh extraction in leaf cells (mesh.hip).
@@ -328,6 +344,8 @@ hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix,
 spk_status launch_converge(const spk_net* net, uint8_t* labels, const uint64_t* cells, int64_t n, int level,
                            const float (&dom_lo)[3], const float (&dom_hi)[3], float* fpts, float* fvals,
                            hipStream_t stream, int num_cus);
+spk_status launch_sample_chunk(const spk_net* net, const SampleJob& J, int64_t i0, int64_t m, float* pts, float* vals,
+                               hipStream_t stream, int num_cus);
 spk_status launch_mesh_chunk(const spk_net* net, const MeshJob& M, int64_t l0, int64_t nl, float* pts, float* vals,
                              hipStream_t stream, int num_cus);
 spk_status launch_ix_round(const IxRound& X, hipStream_t stream, int num_cus);

@@ -88,7 +88,7 @@ NO_INTERSECTION, INTERSECTION, INTERSECTION_UNDECIDED = 0, 1, 2
 
 class TreeParams(ctypes.Structure):
     _fields_ = [("dom_lo", ctypes.c_float * 3), ("dom_hi", ctypes.c_float * 3), ("max_level", ctypes.c_int32),
-                ("arity", ctypes.c_int32), ("delta", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("arity", ctypes.c_int32), ("delta", ctypes.c_float), ("band", ctypes.c_float)]
 
 
 class RayParams(ctypes.Structure):
@@ -319,13 +319,13 @@ def range_bound(ctx, net, center, axes, lo, hi, policy="truncate", k=31, aux=Non
 
 def subdivide_frontier(ctx, net, level, cells, children, leaves, counts, max_level, policy="truncate", k=31,
                        dom_lo=(-1.0, -1.0, -1.0), dom_hi=(1.0, 1.0, 1.0), arity=8, noalloc=False, rigorous=True,
-                       prec="f32", delta=0.0):
+                       prec="f32", delta=0.0, band=0.0):
     """One round of Procedure 3 (spk_subdivide_frontier, or with
     noalloc=True spk_subdivide_frontier_noalloc); delta > 0 adds the
     convergence test for small cells."""
     import torch
     tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(max_level), int(arity),
-                    float(delta), 0)
+                    float(delta), float(band))
     o = opts(policy, k, rigorous, prec)
     n = cells.shape[0]
     capc = children.shape[0] if children is not None else 0
@@ -708,7 +708,7 @@ def build_octrees_batched(ctx, nets, max_level, policy="truncate", k=31, rigorou
 
 
 def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3,
-                 cap=1 << 26, rigorous=True, prec="f32"):
+                 cap=1 << 26, rigorous=True, prec="f32", band=0.0):
     """Fixed-depth octree by repeated spk_subdivide_frontier rounds (the
     breadth-first parallel rounds of Procedure 3).  Returns per-level stats and
     the UNKNOWN leaf cells at max_level (GPU tensor)."""
@@ -726,7 +726,7 @@ def build_octree(ctx, net, max_level, policy="truncate", k=31, dom_lo=(-1.0,) * 
         children = torch.empty(max(capc, 1), dtype=torch.int64, device=dev)
         lv = torch.empty(max(capl, 1), dtype=torch.int64, device=dev)
         subdivide_frontier(ctx, net, level, cells, children[:capc] if capc else None, lv[:capl] if capl else None,
-                           counts, max_level, policy, k, dom_lo, dom_hi, rigorous=rigorous, prec=prec)
+                           counts, max_level, policy, k, dom_lo, dom_hi, rigorous=rigorous, prec=prec, band=band)
         ds = ctx.sync(allow_nospc=True)
         c = counts.cpu().tolist()
         levels.append({"level": level, "n": n, "n_children": c[0], "n_leaves": c[1], "n_pos": c[2], "n_neg": c[3]})

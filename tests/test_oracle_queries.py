@@ -466,3 +466,47 @@ def test_mesh_octahedron_is_closed_and_exact():
     V, E, F, bad = _mesh_topology(tris)
     assert bad == 0
     assert V - E + F == 2
+
+
+def test_splitmix64_reference_value():
+    """The generator's first output for seed 0 is the published 0xe220a8397b1dcdaf,
+    and consecutive outputs are the documented increments of the state."""
+    assert int(q.splitmix64(0, np.array([0]))[0]) == 0xe220a8397b1dcdaf
+    a = q.splitmix64(12345, np.arange(4))
+    assert len(set(int(x) for x in a)) == 4
+
+
+def test_band_sampling_and_volume_octahedron():
+    """The exact octahedron |x|_1 = R: the bulk volume brackets the exact
+    (4/3) R^3 and its estimate lies within 4 standard errors; the leaves of
+    the band tree (r = 0.05) contain every point of the band that rejection
+    sampling of the whole domain finds; band samples lie in the leaves and
+    have |f| < r."""
+    R = 0.55
+    net = wl.octahedron_mlp(R)
+    vol, lo, hi = q.bulk_volume(net, 4, 20000, 7, "fixed", 0)
+    exact = 4.0 / 3.0 * R ** 3
+    assert lo <= exact <= hi
+    res = q.octree_build(net, 4, "fixed", 0)
+    v_leaf = res["leaves"].size * 8.0 / 8.0 ** 4
+    p_in = (exact - lo) / v_leaf
+    se = v_leaf * math.sqrt(p_in * (1 - p_in) / 20000)
+    assert abs(vol - exact) <= 4 * se + 1e-12
+    r = 0.05
+    bt = q.octree_build(net, 4, "fixed", 0, band=r)
+    lo_c, hi_c = q.cell_bounds(bt["leaves"], 4, (-1,) * 3, (1,) * 3)
+
+    def in_leaves(x):
+        m = np.zeros(len(x), bool)
+        for a, b in zip(lo_c, hi_c):
+            m |= np.all((x >= a) & (x <= b), axis=1)
+        return m
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, (200000, 3))
+    xb = x[np.abs(np.abs(x).sum(axis=1) - R) < r]
+    assert xb.shape[0] > 1000 and in_leaves(xb).all()
+    pts, f, ok = q.sample_leaves(net, bt["leaves"], 4, 5000, 3, band=r)
+    assert in_leaves(pts).all() and ok.sum() > 1000
+    assert np.all(np.abs(np.abs(pts[ok]).sum(axis=1) - R) < r + 1e-12)
+    # the band tree keeps every cell of the level-set tree
+    assert np.isin(res["leaves"], bt["leaves"]).all()
