@@ -179,6 +179,20 @@ def queries_extra(ctx, g, dev):
                    "grid_points": int(leaves6.shape[0]) * 729, "triangles": int(tris.shape[0]), "seconds": dt,
                    "grid_points_per_s": int(leaves6.shape[0]) * 729 / dt}
     del tris
+    # surface sampling (band 0.01) and bulk volume at depth 7, paper arithmetic
+    t = time.perf_counter()
+    lvb, leaves_b = spk.build_octree(ctx, g, 7, "truncate", K_KEEP, rigorous=False, band=0.01)
+    pts, _, _ = spk.sample_leaves(ctx, g, leaves_b, 7, 1 << 22, seed=5, band=0.01)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    out["surface_sampling"] = {"band": 0.01, "tree_depth": 7, "leaves": int(leaves_b.shape[0]),
+                               "candidates": 1 << 22, "accepted": int(pts.shape[0]), "seconds": dt,
+                               "acceptance": pts.shape[0] / float(1 << 22),
+                               "leaf_volume_fraction": leaves_b.shape[0] / 8.0 ** 7}
+    t = time.perf_counter()
+    v, vlo, vhi = spk.bulk_volume(ctx, g, 7, 1 << 22, seed=6, policy="truncate", k=K_KEEP, rigorous=False)
+    out["bulk_volume"] = {"depth": 7, "samples": 1 << 22, "estimate": v, "lower": vlo, "upper": vhi,
+                          "seconds": time.perf_counter() - t}
     spec = wl.scale_net(1)
     shifted = wl.MLPSpec([w.copy() for w in spec.weights], [b.copy() for b in spec.biases], act=spec.act)
     shifted.biases[0] = (shifted.biases[0] - shifted.weights[0] @ np.array([0.3, 0.0, 0.0], np.float32)).astype(

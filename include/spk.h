@@ -300,6 +300,7 @@ typedef struct {
  * unspecified order, to points dev [cap][3] and f dev [cap] (nullable).
  *   n_accepted host: accepted samples (SPK_E_NOSPC when above cap; the first
  *              cap are written); n_below host nullable: accepted with f < 0.
+ *   points = NULL (cap 0): only the counts are computed.
  * Synchronous; 16 bytes per sample of a chunk of at most 2^24 samples,
  * stream-ordered within the context's workspace limit.
  */

@@ -941,7 +941,8 @@ spk_status spk_sample_leaves(spk_ctx* ctx, const spk_net* net, const spk_tree_pa
   *n_accepted = (int64_t)c[0];
   if (n_below) *n_below = (int64_t)c[1];
   net_mark_use(net, ctx->stream);
-  return (int64_t)c[0] > cap ? SPK_E_NOSPC : SPK_OK;
+  // points == NULL: the counts alone were asked for
+  return (points != nullptr && (int64_t)c[0] > cap) ? SPK_E_NOSPC : SPK_OK;
 }
 
 // Mesh extraction in leaf cells (Section 4.7); kernels in mesh.hip.

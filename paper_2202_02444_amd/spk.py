@@ -8,6 +8,7 @@ missing the first call raises -- there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -24,7 +25,7 @@ UNKNOWN, POSITIVE, NEGATIVE = 0, 1, 2
 EXPORTS = ("spk_status_str", "spk_version", "spk_net_create", "spk_net_destroy", "spk_ctx_create",
            "spk_ctx_destroy", "spk_ctx_sync", "spk_range_bound", "spk_classify_boxes",
            "spk_subdivide_frontier", "spk_subdivide_frontier_noalloc", "spk_cast_rays", "spk_cast_frusta",
-           "spk_empty_spheres", "spk_intersect", "spk_mesh_leaves",
+           "spk_empty_spheres", "spk_intersect", "spk_mesh_leaves", "spk_sample_leaves",
            "spk_eval_points", "spk_closest_point",
            "spk_batch_create", "spk_batch_update", "spk_batch_launch", "spk_batch_tune", "spk_batch_classes",
            "spk_batch_destroy", "spk_server_create", "spk_server_submit", "spk_server_poll",
@@ -141,6 +142,8 @@ def lib():
         L.spk_subdivide_frontier_noalloc.argtypes = [vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams), i32, vp,
                                              i64, vp, i64, vp, i64, vp]
         L.spk_cast_rays.argtypes = [vp, vp, ctypes.POINTER(RayParams), i64, vp, vp, vp, vp]
+        L.spk_sample_leaves.argtypes = [vp, vp, ctypes.POINTER(TreeParams), i32, i64, vp, i64, ctypes.c_uint64,
+                                        ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.spk_mesh_leaves.argtypes = [vp, vp, ctypes.POINTER(TreeParams), i32, i32, i64, vp, vp, vp, i64,
                                       ctypes.POINTER(i64)]
         L.spk_intersect.argtypes = [vp, vp, vp, ctypes.POINTER(BoundOpts), ctypes.POINTER(TreeParams),
@@ -358,6 +361,44 @@ def cast_rays(ctx, net, origin, direction, t_hit, iters=None, **params):
                              _ptr(direction, torch.float32, (n, 3), "direction"),
                              _ptr(t_hit, torch.float32, (n,), "t_hit"), _ptr(iters, torch.int32, (n,), "iters"))
     _check(st, "spk_cast_rays")
+
+
+def sample_leaves(ctx, net, leaves, level, n_samples, seed=0, band=math.inf, cap=None, dom_lo=(-1.0, -1.0, -1.0),
+                  dom_hi=(1.0, 1.0, 1.0)):
+    """spk_sample_leaves: (points [m, 3], f [m], n_below) of the accepted
+    samples (|f| < band) among n_samples uniform points in the leaf cells."""
+    import torch
+    dev = torch.device("cuda")
+    n = leaves.shape[0]
+    tp = TreeParams((ctypes.c_float * 3)(*dom_lo), (ctypes.c_float * 3)(*dom_hi), int(level), 8)
+    cap = int(cap if cap is not None else n_samples)
+    pts = torch.empty((cap, 3), device=dev) if cap > 0 else None
+    f = torch.empty(cap, device=dev) if cap > 0 else None
+    na, nb = ctypes.c_int64(), ctypes.c_int64()
+    st = lib().spk_sample_leaves(ctx.handle, net.handle, ctypes.byref(tp), int(level), n,
+                                 _ptr(leaves, torch.int64, (n,), "leaves"), int(n_samples), int(seed) & (2 ** 64 - 1),
+                                 float(band), _ptr(pts, torch.float32, None, "points"), _ptr(f, torch.float32, None, "f"),
+                                 cap, ctypes.byref(na), ctypes.byref(nb))
+    _check(st, "spk_sample_leaves")
+    if pts is None:
+        return None, None, int(nb.value)
+    return pts[:na.value], f[:na.value], int(nb.value)
+
+
+def bulk_volume(ctx, net, max_level, n_samples, seed=0, policy="truncate", k=31, rigorous=True, prec="f32",
+                dom_lo=(-1.0,) * 3, dom_hi=(1.0,) * 3):
+    """Volume of the solid {f < 0} (Section 4.8) from a fixed-depth tree:
+    NEGATIVE cells in full, the UNKNOWN leaves by the fraction of uniform
+    samples in them with f < 0.  Returns (estimate, lower bound, upper bound)."""
+    levels, leaves = build_octree(ctx, net, max_level, policy, k, dom_lo, dom_hi, rigorous=rigorous, prec=prec)
+    dom = float(np.prod(np.asarray(dom_hi, dtype=np.float64) - np.asarray(dom_lo, dtype=np.float64)))
+    v_neg = sum(lv["n_neg"] * dom / 8.0 ** lv["level"] for lv in levels)
+    v_leaf = leaves.shape[0] * dom / 8.0 ** max_level
+    if leaves.shape[0] == 0:
+        return v_neg, v_neg, v_neg
+    _, _, n_below = sample_leaves(ctx, net, leaves, max_level, n_samples, seed, math.inf, cap=0,
+                                  dom_lo=dom_lo, dom_hi=dom_hi)
+    return v_neg + v_leaf * n_below / n_samples, v_neg, v_neg + v_leaf
 
 
 def mesh_leaves(ctx, net, leaves, level, dense_levels=3, cap=None, dom_lo=(-1.0, -1.0, -1.0),

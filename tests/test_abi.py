@@ -131,6 +131,33 @@ def test_tree_and_ray_validation():
     assert spk.ray_params(rigorous=False).flags == spk.FLAG_NO_ROUNDING_BOUND and spk.ray_params().flags == 0
 
 
+def test_sampling_and_band_validation():
+    L = spk.lib()
+    tp = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 4, 8)
+    na, nb = ctypes.c_int64(), ctypes.c_int64()
+    f = ctypes.c_float
+    call = lambda lvl, nl, lv, ns, band, pts, cap, out: L.spk_sample_leaves(FAKE, FAKE, ctypes.byref(tp), lvl, nl, lv,
+                                                                            ns, 7, f(band), pts, None, cap, out,
+                                                                            ctypes.byref(nb))
+    assert call(3, 4, FAKE, 10, 0.1, FAKE, 10, None) == spk.E_INVAL              # no count output
+    assert call(3, 4, FAKE, 10, 0.0, FAKE, 10, ctypes.byref(na)) == spk.E_INVAL  # empty band
+    assert call(3, 0, None, 10, 0.1, FAKE, 10, ctypes.byref(na)) == spk.E_INVAL  # samples without leaves
+    assert call(3, 4, FAKE, 10, 0.1, None, 10, ctypes.byref(na)) == spk.E_INVAL  # capacity without a buffer
+    assert call(21, 4, FAKE, 10, 0.1, FAKE, 10, ctypes.byref(na)) == spk.E_INVAL
+    assert call(3, 4, FAKE, 0, 0.1, None, 0, ctypes.byref(na)) == spk.OK and na.value == 0
+    o = spk.opts("truncate", 31)
+    cnt = FAKE
+    band_delta = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8, 0.01, 0.05)
+    assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(band_delta), 0, FAKE, 1, FAKE, 8, None,
+                                    0, cnt) == spk.E_INVAL
+    neg = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8, 0.0, -0.5)
+    assert L.spk_subdivide_frontier(FAKE, FAKE, ctypes.byref(o), ctypes.byref(neg), 0, FAKE, 1, FAKE, 8, None, 0,
+                                    cnt) == spk.E_INVAL
+    band = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 6, 8, 0.0, 0.05)
+    r = spk.IntersectResult()
+    assert L.spk_intersect(FAKE, FAKE, FAKE, ctypes.byref(o), ctypes.byref(band), ctypes.byref(r)) == spk.E_INVAL
+
+
 def test_mesh_validation():
     L = spk.lib()
     tp = spk.TreeParams((ctypes.c_float * 3)(-1, -1, -1), (ctypes.c_float * 3)(1, 1, 1), 4, 8)

@@ -555,3 +555,51 @@ def test_delta_tree_vs_oracle(ctx, netname):
                 mn = np.where((lo <= 0) & (hi >= 0), 0.0, np.minimum(np.abs(lo), np.abs(hi))).sum(axis=1)
                 assert np.all(mn <= 0.55 + 1e-6) and np.all(mx >= 0.55 - 1e-6)
     g.close()
+
+
+@pytest.mark.parametrize("netname", ["octa", "tiny"])
+def test_band_tree_sampling_and_volume(ctx, netname):
+    """Surface sampling (Section 4.6) and bulk volume (Section 4.8): the band
+    tree's per-level counts equal the oracle's (paper arithmetic); the GPU's
+    samples are the oracle's splitmix64 samples (the same points up to FP32
+    rounding, the same acceptance outside |f| within rounding of the band);
+    the rounding-bounded band tree's leaves contain the oracle's; and the
+    volume estimate equals the oracle's up to the samples at rounding level."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = {"octa": wl.octahedron_mlp(0.55, pad_to=32), "tiny": wl.tiny_net(0)}[netname]
+    g = spk.Net.from_spec(net)
+    # a band edge off the octahedron's exact cell values (|x|_1 - R is a
+    # multiple of 1/32 - 0.55 at the cell corners), where FP32 and FP64 could
+    # take either side
+    r, depth = 0.0437, 5
+    levels, leaves = spk.build_octree(ctx, g, depth, "truncate", 31, rigorous=False, band=r)
+    res = oq.octree_build(net, depth, "truncate", 31, band=r)
+    for a, b in zip(levels, res["levels"]):
+        assert abs(a["n"] - b["n"]) <= 8 and abs(a["n_pos"] - b["n_pos"]) <= 8, (a, b)
+    lv = np.sort(leaves.cpu().numpy().astype(np.uint64))
+    assert np.setxor1d(lv, res["leaves"]).size <= 8
+    _, rig_leaves = spk.build_octree(ctx, g, depth, "truncate", 31, rigorous=True, band=r)
+    assert np.isin(res["leaves"], rig_leaves.cpu().numpy().astype(np.uint64)).all()
+    leaves_t = torch.from_numpy(res["leaves"].astype(np.int64)).cuda()
+    n = 20000
+    pts, f, nb = spk.sample_leaves(ctx, g, leaves_t, depth, n, seed=11, band=math.inf)
+    po, fo, ok = oq.sample_leaves(net, res["leaves"], depth, n, 11)
+    assert pts.shape[0] == n
+    # the accepted set of band = inf is every sample, written in unspecified
+    # order: every GPU point has an oracle point within FP32 rounding, one to one
+    from scipy.spatial import cKDTree
+    d, idx = cKDTree(po).query(pts.cpu().numpy().astype(np.float64))
+    assert np.max(d) < 1e-6 and np.unique(idx).size == n
+    assert abs(nb - int((fo < 0).sum())) <= max(2, n // 2000)
+    pb, fb, _ = spk.sample_leaves(ctx, g, leaves_t, depth, n, seed=11, band=r)
+    amb = np.abs(np.abs(fo) - r) < 1e-5
+    assert abs(pb.shape[0] - int((np.abs(fo) < r).sum())) <= int(amb.sum()) + 2
+    assert np.all(np.abs(fb.cpu().numpy()) < r)
+    v, lo, hi = spk.bulk_volume(ctx, g, depth, n, seed=11, policy="truncate", k=31, rigorous=False)
+    vo, loo, hio = oq.bulk_volume(net, depth, n, 11, "truncate", 31)
+    assert abs(lo - loo) <= 8 * 8.0 / 8 ** depth and abs(hi - hio) <= 8 * 8.0 / 8 ** depth
+    assert abs(v - vo) <= 0.01 * max(vo, 1e-3) + 16 * 8.0 / 8 ** depth
+    if netname == "octa":
+        assert lo <= 4.0 / 3.0 * 0.55 ** 3 <= hi
+    g.close()
