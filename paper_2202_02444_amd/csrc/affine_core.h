@@ -70,11 +70,94 @@ __device__ __forceinline__ int taddr(int b, int C, int ch) {
   return (b * S::NS + C) * S::H + ((ch ^ (C & S::SWM)) << 2);
 }
 
+// Cross-lane sums on the VALU: DPP moves inside a 16-lane row and the gfx950
+// row-swap instructions between rows, instead of LDS permutes (each of which
+// the compiler waits for before the next one).  Lane groups of 2^m lanes are
+// combined pairwise exactly as by an XOR butterfly over the masks 1, 2, ...,
+// so every lane of a segment holds the same bits, and the same bits as the
+// butterfly.  DPP controls: quad_perm [1,0,3,2] and [2,3,0,1] pair lanes
+// c ^ 1 and c ^ 2; once quads (halves of a row) hold one value each, the
+// half-row mirror (c -> 7 - c) and the row mirror (c -> 15 - c) pair the two
+// quads of each half and the two halves of each row.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __uint_as_float(dpp_u32<CTRL>(__float_as_uint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = dpp_u32<CTRL>((uint32_t)u), hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRowMirror = 0x140, kDppHalfMirror = 0x141;
+
+// The values of this lane's partner row (rows 2r and 2r+1 of 16 lanes pair up)
+// and partner half (lanes l and l ^ 32), from v_permlane16_swap_b32 and
+// v_permlane32_swap_b32 with both operands v: one returned operand holds the
+// even row's (lower half's) value and the other the odd row's (upper half's),
+// in every lane of the pair, so their sum is the same in both.
+__device__ __forceinline__ float row_pair_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float half_pair_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double row_pair_sum(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+  return __longlong_as_double((long long)((uint64_t)l[0] | ((uint64_t)h[0] << 32))) +
+         __longlong_as_double((long long)((uint64_t)l[1] | ((uint64_t)h[1] << 32)));
+}
+__device__ __forceinline__ double half_pair_sum(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+  return __longlong_as_double((long long)((uint64_t)l[0] | ((uint64_t)h[0] << 32))) +
+         __longlong_as_double((long long)((uint64_t)l[1] | ((uint64_t)h[1] << 32)));
+}
+
+// Sum over the SEG consecutive lanes of this lane's segment (SEG = 8, 16, 32
+// or 64), the same value in every lane of it.
+template <int SEG, class T>
+__device__ __forceinline__ T seg_allsum_t(T v) {
+  static_assert(SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segments of 8 to 64 lanes");
+  if constexpr (sizeof(T) == 4) {
+    v += dpp_f<kDppXor1>(v);
+    v += dpp_f<kDppXor2>(v);
+    v += dpp_f<kDppHalfMirror>(v);
+    if constexpr (SEG >= 16) v += dpp_f<kDppRowMirror>(v);
+  } else {
+    v += dpp_d<kDppXor1>(v);
+    v += dpp_d<kDppXor2>(v);
+    v += dpp_d<kDppHalfMirror>(v);
+    if constexpr (SEG >= 16) v += dpp_d<kDppRowMirror>(v);
+  }
+  if constexpr (SEG >= 32) v = row_pair_sum(v);
+  if constexpr (SEG == 64) v = half_pair_sum(v);
+  return v;
+}
 template <int SEG>
 __device__ __forceinline__ float seg_allsum(float v) {
-#pragma unroll
-  for (int m = 1; m < SEG; m <<= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  return seg_allsum_t<SEG, float>(v);
+}
+
+// Sum over the four 16-lane rows (lanes l, l ^ 16, l ^ 32, l ^ 48).
+template <class T>
+__device__ __forceinline__ T rows_allsum(T v) {
+  return half_pair_sum(row_pair_sum(v));
+}
+__device__ __forceinline__ float rows_allmax(float v) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+  r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
 // Number of lanes of this lane's segment (SEG consecutive lanes) with p set.

@@ -37,9 +37,7 @@ __device__ __forceinline__ float act_point(float x, float omega0) {
 
 template <int SEG>
 __device__ __forceinline__ double seg_allsum_d(double v) {
-#pragma unroll
-  for (int m = 1; m < SEG; m <<= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  return seg_allsum_t<SEG, double>(v);
 }
 
 // Round a double to a float that is <= / >= it.
@@ -313,10 +311,8 @@ __device__ __forceinline__ int activate(double (&xc)[4], f4 (&y)[S::NS], float (
 // K-row groups of the wave and store them in the LDS vectors.
 template <class S>
 __device__ __forceinline__ void store_partials(LdsState<S>& sm, int b, int tp, int g, int c, float sx, double sd) {
-  sx += __shfl_xor(sx, 16, 64);
-  sd += __shfl_xor(sd, 16, 64);
-  sx += __shfl_xor(sx, 32, 64);
-  sd += __shfl_xor(sd, 32, 64);
+  sx = rows_allsum(sx);
+  sd = rows_allsum(sd);
   if (g == 0) {
     sm.vinf[b * S::H + 16 * tp + c] = sx;
     sm.vc[b * S::H + 16 * tp + c] = sd;
@@ -650,8 +646,7 @@ __device__ __forceinline__ float single_box_pass_f16(LdsState<S>& sm, const f4* 
 #pragma unroll
     for (int j = 0; j < 4; ++j) m = fmaxf(m, fmaxf(fabsf(b0[j]), fabsf(b1[j])));
   }
-  m = fmaxf(m, __shfl_xor(m, 16, 64));
-  m = fmaxf(m, __shfl_xor(m, 32, 64));
+  m = rows_allmax(m);
   const int ex = (int)((__float_as_uint(m) >> 23) & 0xffu) - 127;   // floor(log2 m); -127 for 0
   const int sh = min(14 - ex, 126);
   const float sc = __uint_as_float((uint32_t)(sh + 127) << 23);
@@ -659,8 +654,7 @@ __device__ __forceinline__ float single_box_pass_f16(LdsState<S>& sm, const f4* 
   // sum of isc over the generator columns (column 0 of the first tile holds
   // the center, whose product is not used) with a nonzero entry
   float ssum = (m > 0.0f && (n > 0 || c > 0)) ? isc : 0.0f;
-#pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) ssum += __shfl_xor(ssum, off, 64);
+  ssum = seg_allsum<16>(ssum);
   f4 acc[MT];
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) acc[tp] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
@@ -749,9 +743,7 @@ __device__ __forceinline__ void single_box_pass_f64(LdsState<S>& sm, const f4* W
 #pragma unroll
   for (int tp = 0; tp < MT; ++tp) {
     if (VA != VA_NONE) {
-      float sx = px[tp];
-      sx += __shfl_xor(sx, 16, 64);
-      sx += __shfl_xor(sx, 32, 64);
+      const float sx = rows_allsum(px[tp]);
       if (g == 0) sm.vinf[16 * tp + c] = sx;
     }
     // the FP64 MFMA's accumulator layout differs from the FP32 one (measured):

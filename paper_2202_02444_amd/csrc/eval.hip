@@ -79,8 +79,7 @@ __global__ __launch_bounds__(64) void eval_kernel(NetDev net, int64_t n, const f
 #pragma unroll
         for (int j = 0; j < 4; ++j) s = fmaf(w[j], in[t][nn][j], s);
       }
-      s += __shfl_xor(s, 16, 64);
-      s += __shfl_xor(s, 32, 64);
+      s = rows_allsum(s);
       const int64_t p = pass * PPP + 16 * nn + c;
       if (g == 0 && p < n) f[p] = s + net.bL;
     }
