@@ -973,11 +973,8 @@ __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S
     a0[i] = 0.0; a1[i] = 0.0; a2[i] = 0.0; a3[i] = 0.0;
     px[i] = 0.0f;
   }
-#pragma unroll 2
-  for (int kb = 0; kb < H / 4; ++kb) {
-    f4 w[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) w[i] = Wr[(size_t)kb * H + i];
+  // one k block (4 columns of W, rows 4ch..4ch+3) of the products
+  auto block = [&](int kb, const f4 (&w)[4]) {
     const f4 d1 = *(const f4*)&dense[4 * kb];
     const f4 d2 = *(const f4*)&dense[H + 4 * kb];
     const f4 d3 = *(const f4*)&dense[2 * H + 4 * kb];
@@ -996,20 +993,61 @@ __device__ __forceinline__ void first_hidden_layer(const NetDev& net, LdsState<S
         px[i] = fmaf(fabsf(w[i][j]), xi[j], px[i]);
       }
     }
+  };
+  // four k blocks per step: their 16 weight loads are in flight together
+  static_assert((H / 4) % 4 == 0, "k blocks in fours");
+#pragma unroll 1
+  for (int kb = 0; kb < H / 4; kb += 4) {
+    f4 w[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[b][i] = Wr[(size_t)(kb + b) * H + i];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) block(kb + b, w[b]);
   }
   // ---- single-entry columns: y[C] = W[:, j] gamma_j; slots past klast are
-  // empty (assigned here so that no slot stays live across the loop above) ----
+  // empty (assigned here so that no slot stays live across the loop above).
+  // With one box per wave the products go through the slots' own (free) LDS
+  // rows, four slots per step, so that the step's 16 weight loads are in
+  // flight together; slots past klast load row 0 and store zeros.
+  if constexpr (S::BPW == 1) {
+    static_assert((NS - 4) % 4 == 0, "slots in fours");
+    static_assert(3 * H + 2 * NS <= 4 * H, "the dense columns and the table lie below slot 4");
+#pragma unroll 1
+    for (int C0 = 4; C0 < NS; C0 += 4) {
+      f4 v[4];
 #pragma unroll
-  for (int C = 4; C < NS; ++C) {
-    f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (C <= klast) {
-      const float g = sent[C];
-      const int j = ((const int*)sent)[NS + C];
-      const float* wc = net.Wr + ((size_t)(j >> 2) * H + 4 * ch) * 4 + (j & 3);
+      for (int q = 0; q < 4; ++q) {
+        const int C = C0 + q;
+        const bool on = C <= klast;
+        const float g = sent[C];
+        const int j = on ? ((const int*)sent)[NS + C] : 0;
+        const float* wc = net.Wr + ((size_t)(j >> 2) * H + 4 * ch) * 4 + (j & 3);
+        // the load is used unconditionally (a select of it becomes a branch
+        // around it); the FMA with +0 turns the zero product into +0
+        const float gs = on ? g : 0.0f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = wc[4 * i] * g;
+        for (int i = 0; i < 4; ++i) v[q][i] = fmaf(wc[4 * i], gs, 0.0f);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(f4*)&sm.tile[taddr<S>(0, C0 + q, ch)] = v[q];
     }
-    y[C] = v;
+#pragma unroll
+    for (int C = 4; C < NS; ++C) y[C] = *(const f4*)&sm.tile[taddr<S>(0, C, ch)];
+  } else {
+#pragma unroll
+    for (int C = 4; C < NS; ++C) {
+      f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (C <= klast) {
+        const float g = sent[C];
+        const int j = ((const int*)sent)[NS + C];
+        const float* wc = net.Wr + ((size_t)(j >> 2) * H + 4 * ch) * 4 + (j & 3);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = wc[4 * i] * g;
+      }
+      y[C] = v;
+    }
   }
   __syncthreads();
   const f4 bh = *(const f4*)&net.bh[4 * ch];
