@@ -617,6 +617,7 @@ spk_status spk_subdivide_frontier_noalloc(spk_ctx* ctx, const spk_net* net, cons
                                        cap_leaves, counts);
   if (st != SPK_OK) return st;
   if (tree->delta != 0.0f) return SPK_E_UNSUPPORTED;   // its face buffers would need an allocation
+  if (opts->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;   // so would affine-full's workspace
   if (n > (int64_t)SPK_NOALLOC_MAX_CELLS) return SPK_E_LIMIT;
   void* labels = nullptr;
   st = noalloc_scratch(ctx->device, &labels);

@@ -323,6 +323,7 @@ spk_status spk_batch_create(spk_ctx* ctx, const spk_bound_opts* opts, int32_t n_
   spk_status st = spk::valid_opts(opts);
   if (st != SPK_OK) return st;
   if (opts->prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;   // the class kernels are FP32
+  if (opts->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;   // no growing generator matrices
   for (int i = 0; i < n_items; ++i) {
     st = valid_item(items[i]);
     if (st != SPK_OK) return st;

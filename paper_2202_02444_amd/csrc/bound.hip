@@ -88,6 +88,7 @@ static hipError_t launch_h(const NetDev& net, const BoundJob& job, hipStream_t s
 }
 
 spk_status launch_bound(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus) {
+  if (job.policy == SPK_AFFINE_FULL) return launch_full(net, job, stream, num_cus);
   if (job.n <= 0) return SPK_OK;
   hipError_t err;
   if (job.prec == SPK_PREC_BF16X3 || job.prec == SPK_PREC_F16X3 || job.prec == SPK_PREC_F64) {

@@ -309,8 +309,10 @@ inline spk_status valid_opts(const spk_bound_opts* o) {
   if (o == nullptr) return SPK_E_INVAL;
   if (o->prec != SPK_PREC_F32 && o->prec != SPK_PREC_BF16X3 && o->prec != SPK_PREC_F16X3 && o->prec != SPK_PREC_F64)
     return SPK_E_UNSUPPORTED;
-  if (o->policy == SPK_AFFINE_FULL) return SPK_E_UNSUPPORTED;
-  if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE) return SPK_E_INVAL;
+  if (o->policy != SPK_AFFINE_FIXED && o->policy != SPK_AFFINE_TRUNCATE && o->policy != SPK_AFFINE_FULL)
+    return SPK_E_INVAL;
+  // affine-full: FP32 generator products only
+  if (o->policy == SPK_AFFINE_FULL && o->prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;
   if (o->policy == SPK_AFFINE_TRUNCATE && (o->k < 3 || o->k > 31)) return SPK_E_UNSUPPORTED;
   if (o->flags & ~(uint32_t)(SPK_FLAG_RIGOROUS | SPK_FLAG_NO_ROUNDING_BOUND)) return SPK_E_INVAL;
   if (o->flags & SPK_FLAG_NO_ROUNDING_BOUND) {
@@ -324,6 +326,9 @@ void net_mark_use(const spk_net* net, hipStream_t stream);
 
 // Launch helpers implemented in bound.hip / tree.hip / rays.hip.
 spk_status launch_bound(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus);
+// affine-full (full.hip): hidden width 256, FP32 products; allocates its
+// workspace stream-ordered for the launch
+spk_status launch_full(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus);
 spk_status launch_compact(const uint8_t* labels, const uint64_t* cells, int64_t n, bool at_max,
                           uint64_t* children, int64_t cap_children, uint64_t* leaves, int64_t cap_leaves,
                           int64_t* counts, void* status, hipStream_t stream, int num_cus);

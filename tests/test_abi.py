@@ -68,7 +68,7 @@ def test_bound_calls_validate_before_launch():
     bad = spk.opts("truncate", 40)
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(bad), 4, FAKE, FAKE, FAKE, None, None,
                                 None) == spk.E_UNSUPPORTED
-    full = spk.opts("full", 0)
+    full = spk.opts("full", 0, prec="f16x3")   # affine-full: FP32 products only
     assert L.spk_classify_boxes(FAKE, FAKE, ctypes.byref(full), 4, FAKE, FAKE, FAKE, None, None,
                                 None) == spk.E_UNSUPPORTED
     badprec = spk.BoundOpts(1, 31, 4, 0)   # no spk_prec 4
@@ -247,7 +247,7 @@ def test_frustum_validation():
     bad = spk.camera(wl.camera(8, 6, 1))
     bad.width = 0
     assert call(rp, o, bad, 1, 1, FAKE) == spk.E_INVAL
-    full = spk.opts("full", 0)
+    full = spk.opts("full", 0, prec="bf16x3")
     assert call(rp, full, cam, 2, 2, FAKE) == spk.E_UNSUPPORTED
 
 

@@ -1,0 +1,130 @@
+"""GPU parity of the affine-full bound (Section 3.3: no condensation, every
+new term kept) against the FP64 oracle's full policy, through the C ABI.
+Tolerances as for the other policies: raw endpoints within 1e-5 * S in the
+paper's arithmetic, labels equal outside the ambiguity band, the rounding-
+bounded bound containing the oracle's exact bound, and every sampled f inside
+the returned bound.  Hidden width 256 (one box per wave); other widths and
+the split precisions return SPK_E_UNSUPPORTED."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as omlp
+
+from parity import (TOL, default_margin, endpoint_errors, gpu_classify, label_ambiguous, oracle_labels,
+                    rigorous_vs_oracle, s_net, soundness_violations)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2202_02444_amd import spk
+    c = spk.Context()
+    yield c
+    c.close()
+
+
+def _net(act, depth, seed):
+    widths = [3] + [256] * depth + [1]
+    if act == "sin":
+        return wl.siren_mlp(widths, seed, omega0=30.0)
+    return wl.he_normal_mlp(widths, seed, act=act)
+
+
+def _check(ctx, net, lo, hi, rng, name, sample=None):
+    """GPU full bounds of every box; the oracle's of the boxes in `sample`
+    (default all) compared with them."""
+    from paper_2202_02444_amd import spk
+    g = spk.Net.from_spec(net)
+    out = gpu_classify(ctx, g, lo, hi, "full", 0)
+    outr = gpu_classify(ctx, g, lo, hi, "full", 0, rigorous=True)
+    if sample is not None:
+        out = {key: v[sample] for key, v in out.items()}
+        outr = {key: v[sample] for key, v in outr.items()}
+        lo, hi = lo[sample], hi[sample]
+    c_o, r_o, lo_o, hi_o = omlp.bound_boxes(net, lo, hi, "full")
+    S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+    free = endpoint_errors(out["center"], out["radius"], lo_o, hi_o, S)
+    amb = label_ambiguous(lo_o, hi_o, S, default_margin(out))
+    assert np.array_equal(out["label"][~amb], oracle_labels(lo_o, hi_o)[~amb]), name
+    viol, ratio = rigorous_vs_oracle(outr, lo_o, hi_o, S)
+    bad, _ = soundness_violations(net, lo, hi, outr["lo"], outr["hi"], rng)
+    print("%s: paper max err %.2e (tol %.0e); rounding-bounded containment %.2e, width ratio median %.4f "
+          "p99 %.4f; %d sampled f outside" % (name, free.max(), TOL, viol.max(), np.median(ratio),
+                                               np.quantile(ratio, 0.99), bad))
+    assert free.max() <= TOL, (name, free.max())
+    assert viol.max() <= TOL, (name, viol.max())
+    assert np.median(ratio) <= 1.05, name
+    assert bad == 0, name
+    return out, outr, (lo_o, hi_o)
+
+
+@pytest.mark.parametrize("act", ["relu", "elu", "sin"])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_full_parity(ctx, act, depth):
+    net = _net(act, depth, 40 + depth)
+    lo, hi = wl.boxes(96, 70 + depth, 1e-3, 0.3)
+    _check(ctx, net, lo, hi, np.random.default_rng(5), "%s 256x%d" % (act, depth))
+
+
+def test_full_blob_8x256(ctx):
+    """The 3 -> 256 x 8 -> 1 blob: the generator matrix grows to 1824 columns."""
+    net = wl.scale_net(1)
+    lo, hi = wl.boxes(12, 11, 1e-3, 0.3)
+    out, outr, (lo_o, hi_o) = _check(ctx, net, lo, hi, np.random.default_rng(6), "blob 256x8")
+    # affine-full is the tightest policy (Table 1): on these boxes its bounds
+    # are narrower than truncate(31)'s
+    _, _, lo_t, hi_t = omlp.bound_boxes(net, lo, hi, "truncate", 31)
+    ratio = (hi_o - lo_o) / (hi_t - lo_t)
+    print("full / truncate(31) width: median %.3f max %.3f" % (np.median(ratio), ratio.max()))
+    assert np.median(ratio) < 1.0
+
+
+def test_full_ragged_many_boxes(ctx):
+    """More boxes than waves (each wave takes a contiguous run of boxes, the
+    last runs one shorter) and boxes of every size, one a single point."""
+    net = _net("relu", 2, 9)
+    lo, hi = wl.boxes(1100, 12, 1e-4, 0.5)
+    lo[7] = hi[7] = 0.25
+    sample = np.r_[np.arange(0, 1100, 9), 7, 1098, 1099]
+    _check(ctx, net, lo, hi, np.random.default_rng(7), "relu 256x2, 1100 boxes", sample)
+
+
+def test_full_octree_matches_oracle(ctx):
+    """Procedure 3 with affine-full cell bounds (paper arithmetic): per-level
+    frontier sizes and the UNKNOWN leaves equal to the oracle's tree up to
+    cells whose oracle bound is within the parity band of zero."""
+    from oracle import queries as oq
+    from paper_2202_02444_amd import spk
+    net = _net("relu", 2, 3)
+    g = spk.Net.from_spec(net)
+    levels, leaves = spk.build_octree(ctx, g, 3, policy="full", k=0, rigorous=False)
+    res = oq.octree_build(net, 3, policy="full", k=0)
+    got = [lv["n"] for lv in levels]
+    exp = [lv["n"] for lv in res["levels"]]
+    print("frontier gpu", got, "oracle", exp)
+    for a, b in zip(got, exp):
+        assert abs(a - b) <= max(2, b // 200), (got, exp)
+    leaves = leaves.cpu().numpy().astype(np.uint64)
+    assert len(np.setxor1d(leaves, res["leaves"])) <= max(2, res["leaves"].size // 200)
+
+
+def test_full_unsupported_widths_and_precisions(ctx):
+    import torch
+    from paper_2202_02444_amd import spk
+    dev = torch.device("cuda")
+    lo, hi = wl.boxes(4, 1, 1e-3, 0.3)
+    tl = torch.from_numpy(lo).to(dev)
+    th = torch.from_numpy(hi).to(dev)
+    lab = torch.empty(4, dtype=torch.uint8, device=dev)
+    g = spk.Net.from_spec(wl.tiny_net(0))   # width 32
+    with pytest.raises(spk.SpkError) as e:
+        spk.classify_boxes(ctx, g, tl, th, lab, policy="full", k=0)
+    assert e.value.status == spk.E_UNSUPPORTED
+    g = spk.Net.from_spec(_net("relu", 1, 0))
+    with pytest.raises(spk.SpkError) as e:
+        spk.classify_boxes(ctx, g, tl, th, lab, policy="full", k=0, prec="bf16x3")
+    assert e.value.status == spk.E_UNSUPPORTED
