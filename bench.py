@@ -333,6 +333,40 @@ def precision_extra(ctx, g, net, tlo, thi, lo, hi, dev, steps=2):
     return res
 
 
+def full_extra(ctx, g, tlo, thi, dev, n=65536, steps=1):
+    """The affine-full policy (Section 3.3: every term kept) on the first n
+    bench boxes, in the paper's arithmetic and rounding-bounded: boxes/s, the
+    share of boxes classified against truncate(31) on the same boxes, and the
+    algorithmic rate: hidden layer a multiplies the 256 x 256 weights into
+    3 + 256 a generator columns (2 FLOP per multiply-add), 707 MFLOP per box
+    over the seven hidden layers."""
+    import torch
+    from paper_2202_02444_amd import spk
+    lo_t, hi_t = tlo[:n].contiguous(), thi[:n].contiguous()
+    H, L = 256, g.n_linear
+    flop = sum(2.0 * H * H * (3 + H * a) for a in range(L - 2))
+    stream = torch.cuda.current_stream()
+    res = {"boxes": n, "flop_per_box": flop}
+    for name, rig in (("paper", False), ("rigorous", True)):
+        lab = torch.empty(n, dtype=torch.uint8, device=dev)
+        spk.classify_boxes(ctx, g, lo_t, hi_t, lab, policy="full", k=0, rigorous=rig)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            spk.classify_boxes(ctx, g, lo_t, hi_t, lab, policy="full", k=0, rigorous=rig)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        labt = torch.empty(n, dtype=torch.uint8, device=dev)
+        spk.classify_boxes(ctx, g, lo_t, hi_t, labt, policy="truncate", k=K_KEEP, rigorous=rig)
+        torch.cuda.synchronize()
+        tf = flop * n / (ms * 1e-3) / 1e12
+        res[name] = {"boxes_per_s": n / (ms * 1e-3), "ms": ms, "tflops": tf, "frac_fp32_mfma": tf * 1e12 / PEAK_FP32_MFMA,
+                     "classified": float((lab != 0).double().mean().item()),
+                     "truncate31_classified": float((labt != 0).double().mean().item())}
+    return res
+
+
 def serving_extra(dev, n_requests=40, loads=(0.3, 0.6, 0.9), budget=512 << 20, seed=500):
     """Poisson arrivals of ray-cast, box-classify and closest-point requests
     (40/40/20 %) against 16 resident networks (4 tiny, 4 blob 8x256, 8 of the
@@ -481,7 +515,7 @@ def main():
     ap.add_argument("--boxes", type=int, default=N_BOXES)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the octree / ray extra measurements")
-    ap.add_argument("--extras", default="octree,rays,frusta,queries,closest,batched,precision,serving",
+    ap.add_argument("--extras", default="octree,rays,frusta,queries,closest,batched,precision,full,serving",
                     help="comma-separated extra measurements to run")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -600,6 +634,8 @@ def main():
             progress("batched done")
         if "precision" in which:
             extra["precision"] = precision_extra(ctx, g, net, tlo, thi, lo, hi, dev)
+        if "full" in which:
+            extra["affine_full"] = full_extra(ctx, g, tlo, thi, dev)
             progress("precision done")
         if "serving" in which:
             extra["serving"] = serving_extra(dev)

@@ -281,6 +281,8 @@ def test_batch_validation():
     assert L.spk_batch_create(None, ctypes.byref(o), 1, items, ctypes.byref(h)) == spk.E_INVAL
     bad = spk.opts("truncate", 40)
     assert L.spk_batch_create(FAKE, ctypes.byref(bad), 1, items, ctypes.byref(h)) == spk.E_UNSUPPORTED
+    full = spk.opts("full", 0)                                        # affine-full is not batched
+    assert L.spk_batch_create(FAKE, ctypes.byref(full), 1, items, ctypes.byref(h)) == spk.E_UNSUPPORTED
     assert L.spk_batch_launch(FAKE, None) == spk.E_INVAL
     assert L.spk_batch_tune(FAKE, None, 3) == spk.E_INVAL
     assert L.spk_batch_destroy(None) == spk.E_INVAL
