@@ -213,12 +213,19 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
       for (int64_t c0t = 0; c0t < ncols; c0t += 32) {
         float* T = Yw + (size_t)c0t * kH + 4 * ch;
         __syncthreads();
+        // eight columns' loads in flight per step
+#pragma unroll 1
+        for (int C0 = 0; C0 < 32; C0 += 8) {
+          f4 buf[8];
 #pragma unroll
-        for (int C = 0; C < 32; ++C) {
-          f4 val = *(const f4*)&T[(size_t)C * kH];
+          for (int q = 0; q < 8; ++q) buf[q] = __builtin_nontemporal_load((const f4*)&T[(size_t)(C0 + q) * kH]);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) val[i] *= al[i];
-          *(f4*)&sm.st.tile[taddr<FS>(0, C, ch)] = val;
+          for (int q = 0; q < 8; ++q) {
+            f4 val = buf[q];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) val[i] *= al[i];
+            *(f4*)&sm.st.tile[taddr<FS>(0, C0 + q, ch)] = val;
+          }
         }
         __syncthreads();
         single_box_pass2<FS, VA_NONE>(sm.st, Wl, lane);
@@ -271,10 +278,14 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
     for (int64_t c0t = 0; c0t < ncols; c0t += 32) {
       const float* T = Yw + (size_t)c0t * kH + 4 * ch;
       float p[32];
+#pragma unroll 1
+      for (int C0 = 0; C0 < 32; C0 += 8) {
+        f4 buf[8];
 #pragma unroll
-      for (int C = 0; C < 32; ++C) {
-        const f4 val = *(const f4*)&T[(size_t)C * kH];
-        p[C] = fmaf(wa[3], val[3], fmaf(wa[2], val[2], fmaf(wa[1], val[1], wa[0] * val[0])));
+        for (int q = 0; q < 8; ++q) buf[q] = __builtin_nontemporal_load((const f4*)&T[(size_t)(C0 + q) * kH]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          p[C0 + q] = fmaf(wa[3], buf[q][3], fmaf(wa[2], buf[q][2], fmaf(wa[1], buf[q][1], wa[0] * buf[q][0])));
       }
 #pragma unroll
       for (int C = 0; C < 32; ++C) rd += (double)fabsf(seg_allsum<64>(p[C]));
