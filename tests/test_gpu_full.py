@@ -128,3 +128,52 @@ def test_full_unsupported_widths_and_precisions(ctx):
     with pytest.raises(spk.SpkError) as e:
         spk.classify_boxes(ctx, g, tl, th, lab, policy="full", k=0, prec="bf16x3")
     assert e.value.status == spk.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_full_rotated_boxes(ctx, s):
+    """spk_range_bound with s random (rotated) axes under affine-full: the
+    paper-arithmetic endpoints against the oracle's bound_general with the
+    full policy, and every sampled f of the parallelepiped inside the
+    rounding-bounded bound."""
+    import torch
+    from paper_2202_02444_amd import spk
+    net = _net("elu", 2, 17)
+    g = spk.Net.from_spec(net)
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(30 + s)
+    n = 64
+    ax = (rng.standard_normal((n, s, 3)) * 0.08).astype(np.float32)
+    cc = rng.uniform(-0.9, 0.9, (n, 3)).astype(np.float32)
+    tc, ta = torch.from_numpy(cc).to(dev), torch.from_numpy(ax).to(dev)
+    lo_p, hi_p = torch.empty(n, device=dev), torch.empty(n, device=dev)
+    lo_r, hi_r = torch.empty(n, device=dev), torch.empty(n, device=dev)
+    spk.range_bound(ctx, g, tc, ta, lo_p, hi_p, "full", 0, rigorous=False)
+    spk.range_bound(ctx, g, tc, ta, lo_r, hi_r, "full", 0, rigorous=True)
+    ctx.sync()
+    lo_o, hi_o = omlp.bound_general(net, cc, ax, "full", 0)
+    S = np.maximum(np.maximum(np.abs(lo_o), np.abs(hi_o)), s_net(net))
+    # paper arithmetic: endpoints within the tolerance plus the 2^-18 margin
+    # the library adds to them
+    marg = 3.9e-6 * (np.abs(lo_o) + np.abs(hi_o)) + TOL * S
+    assert np.all(np.abs(lo_p.cpu().numpy() - lo_o) <= marg)
+    assert np.all(np.abs(hi_p.cpu().numpy() - hi_o) <= marg)
+    lr, hr = lo_r.cpu().numpy(), hi_r.cpu().numpy()
+    assert np.all(lr <= lo_o + TOL * S) and np.all(hr >= hi_o - TOL * S)
+    eps = rng.uniform(-1, 1, (n, 64, s))
+    P = cc[:, None, :].astype(np.float64) + np.einsum("bms,bsd->bmd", eps, ax.astype(np.float64))
+    f = omlp.forward(net, P.reshape(-1, 3)).reshape(n, 64)
+    assert np.all(f >= lr[:, None]) and np.all(f <= hr[:, None])
+
+
+def test_full_rejected_by_noalloc(ctx):
+    import torch
+    from paper_2202_02444_amd import spk
+    g = spk.Net.from_spec(_net("relu", 1, 0))
+    dev = torch.device("cuda")
+    cells = torch.zeros(1, dtype=torch.int64, device=dev)
+    children = torch.empty(8, dtype=torch.int64, device=dev)
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    with pytest.raises(spk.SpkError) as e:
+        spk.subdivide_frontier(ctx, g, 0, cells, children, None, counts, 3, "full", 0, noalloc=True)
+    assert e.value.status == spk.E_UNSUPPORTED
