@@ -696,8 +696,16 @@ struct CpBuffers {
        *fpts = nullptr, *fvals = nullptr, *cnt = nullptr, *dcur = nullptr;
   size_t c_best = 0, c_codes = 0, c_qidx = 0, c_ncodes = 0, c_nqidx = 0, c_labels = 0, c_fpts = 0, c_fvals = 0,
          c_cnt = 0, c_dcur = 0;
+  // distinct cells of a round: sorted codes, distinct codes, their labels and
+  // face values, the sort / unique temporary storage
+  void *sorted = nullptr, *ucodes = nullptr, *ulabels = nullptr, *ufvals = nullptr, *dtemp = nullptr;
+  size_t c_sorted = 0, c_ucodes = 0, c_ulabels = 0, c_ufvals = 0, c_dtemp = 0;
   CallBuffers B;   // last: destroyed first, while the pointers above are alive
 };
+
+// Rounds with at least this many (query, cell) items classify each distinct
+// cell once (sort + unique + gather); below it the items are bounded directly.
+constexpr int64_t kCpShareMin = 4096;
 
 static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_bound_opts* opts,
                                 const spk_tree_params* tree, int64_t n, const float* q, float* point, float* dist,
@@ -812,12 +820,35 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
     }
     job.label = (uint8_t*)labels;
     job.nonfinite = (unsigned long long*)ctx->status;
+    // large rounds: classify and evaluate each distinct cell once
+    const bool shared = m >= kCpShareMin;
+    int64_t nu = 0;
+    if (shared) {
+      SPK_ENSURE(CB.sorted, CB.c_sorted, (size_t)m * 8);
+      SPK_ENSURE(CB.ucodes, CB.c_ucodes, (size_t)m * 8);
+      const size_t tb = cp_dedup_temp_bytes(m);
+      SPK_ENSURE(CB.dtemp, CB.c_dtemp, tb);
+      int64_t* dnu = (int64_t*)((char*)cnt + 64);
+      st = launch_cp_dedup((const uint64_t*)codes, (uint64_t*)CB.sorted, (uint64_t*)CB.ucodes, dnu, m, level,
+                           CB.dtemp, CB.c_dtemp, ctx->stream);
+      if (st != SPK_OK) return st;
+      if (hipMemcpyAsync(&nu, dnu, sizeof(nu), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return SPK_E_DEVICE;
+      if (nu < 1 || nu > m) return SPK_E_DEVICE;
+      SPK_ENSURE(CB.ulabels, CB.c_ulabels, (size_t)nu);
+      SPK_ENSURE(CB.ufvals, CB.c_ufvals, (size_t)nu * 6 * 4);
+      job.n = nu;
+      job.cells = (const uint64_t*)CB.ucodes;
+      job.label = (uint8_t*)CB.ulabels;
+    }
     st = launch_bound(net, job, ctx->stream, ctx->num_cus);
     if (st != SPK_OK) return st;
     CpLevel L = {};
     L.m = m;
     L.level = level;
     L.at_max = at_max ? 1 : 0;
+    L.shared = shared ? 1 : 0;
     for (int d = 0; d < 3; ++d) {
       L.dom_lo[d] = tree->dom_lo[d];
       L.dom_hi[d] = tree->dom_hi[d];
@@ -834,6 +865,16 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
     L.nqidx = (uint32_t*)nqidx;
     L.ncount = (unsigned long long*)cnt;
     L.cap = at_max ? 0 : m * 8;
+    if (shared) {
+      // face centers of the distinct cells in fpts (nu <= m), their values in
+      // ufvals, gathered into every item's labels and fvals
+      CpLevel U = L;
+      U.m = nu;
+      U.codes = (const uint64_t*)CB.ucodes;
+      st = launch_cp_shared(net, U, (const uint64_t*)codes, m, (const uint8_t*)CB.ulabels, (float*)CB.ufvals,
+                            (uint8_t*)labels, (float*)fvals, ctx->stream, ctx->num_cus);
+      if (st != SPK_OK) return st;
+    }
     st = launch_cp_round(net, L, ctx->stream, ctx->num_cus);
     if (st != SPK_OK) return st;
     if (at_max) break;

@@ -15,6 +15,14 @@
 // not lower the bound (its farthest distance is at least its minimum), so the
 // final bound equals that of the best-first order, which only visits cells in
 // a different order.
+//
+// Queries near the same stretch of surface share most of their frontier
+// cells, and a cell's bound and face values do not depend on the query: on
+// large rounds the distinct cells are found (radix sort of the codes, then
+// unique), classified and evaluated once, and every (query, cell) item reads
+// its cell's results by binary search.
+#include <hipcub/hipcub.hpp>
+
 #include "spk_impl.h"
 
 namespace spk {
@@ -272,12 +280,68 @@ spk_status launch_cp_init(int64_t n, uint64_t* codes, uint32_t* qidx, unsigned* 
   return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
 }
 
+// Item i reads the label and face values of its cell from the distinct
+// cells' arrays (ucodes sorted ascending, every item's code among them).
+__global__ __launch_bounds__(256) void cp_gather_kernel(const uint64_t* codes, int64_t m, const uint64_t* ucodes,
+                                                        int64_t nu, const uint8_t* ulabel, const float* ufvals,
+                                                        uint8_t* label, float* fvals) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = codes[i];
+    int64_t lo = 0, hi = nu - 1;   // ucodes[lo] <= c <= ucodes[hi]
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ucodes[mid] < c)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    label[i] = ulabel[lo];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) fvals[6 * i + f] = ufvals[6 * lo + f];
+  }
+}
+
+size_t cp_dedup_temp_bytes(int64_t m) {
+  size_t a = 0, b = 0;
+  (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const uint64_t*)nullptr, (uint64_t*)nullptr, (int)m);
+  (void)hipcub::DeviceSelect::Unique(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr, (int64_t*)nullptr,
+                                     (int)m);
+  return (a > b ? a : b) + 256;
+}
+
+spk_status launch_cp_dedup(const uint64_t* codes, uint64_t* sorted, uint64_t* ucodes, int64_t* nu, int64_t m,
+                           int level, void* temp, size_t temp_bytes, hipStream_t stream) {
+  if (m <= 0 || m > (int64_t)0x7fffffff) return SPK_E_INVAL;
+  size_t tb = temp_bytes;
+  // the codes of level `level` occupy the low 3 level bits
+  const int end_bit = level > 0 ? 3 * level : 1;
+  if (hipcub::DeviceRadixSort::SortKeys(temp, tb, codes, sorted, (int)m, 0, end_bit, stream) != hipSuccess)
+    return SPK_E_DEVICE;
+  tb = temp_bytes;
+  if (hipcub::DeviceSelect::Unique(temp, tb, sorted, ucodes, nu, (int)m, stream) != hipSuccess) return SPK_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+}
+
+spk_status launch_cp_shared(const spk_net* net, const CpLevel& U, const uint64_t* codes, int64_t m,
+                            const uint8_t* ulabel, float* ufvals, uint8_t* label, float* fvals, hipStream_t stream,
+                            int num_cus) {
+  hipLaunchKernelGGL(cp_faces_kernel, dim3(grid_for(U.m, num_cus)), dim3(256), 0, stream, U);
+  if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
+  spk_status st = launch_eval(net, 6 * U.m, U.fpts, ufvals, stream, num_cus);
+  if (st != SPK_OK) return st;
+  hipLaunchKernelGGL(cp_gather_kernel, dim3(grid_for(m, num_cus)), dim3(256), 0, stream, codes, m, U.codes, U.m,
+                     ulabel, ufvals, label, fvals);
+  return hipGetLastError() == hipSuccess ? SPK_OK : SPK_E_DEVICE;
+}
+
 spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t stream, int num_cus) {
   const unsigned g = grid_for(L.m, num_cus);
-  hipLaunchKernelGGL(cp_faces_kernel, dim3(g), dim3(256), 0, stream, L);
-  if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
-  spk_status st = launch_eval(net, 6 * L.m, L.fpts, L.fvals, stream, num_cus);
-  if (st != SPK_OK) return st;
+  if (!L.shared) {
+    hipLaunchKernelGGL(cp_faces_kernel, dim3(g), dim3(256), 0, stream, L);
+    if (hipGetLastError() != hipSuccess) return SPK_E_DEVICE;
+    spk_status st = launch_eval(net, 6 * L.m, L.fpts, L.fvals, stream, num_cus);
+    if (st != SPK_OK) return st;
+  }
   hipLaunchKernelGGL(cp_update_kernel, dim3(g), dim3(256), 0, stream, L);
   hipLaunchKernelGGL(cp_point_kernel, dim3(g), dim3(256), 0, stream, L);
   if (!L.at_max) {

@@ -133,6 +133,7 @@ struct CpLevel {
   int64_t m;                 // frontier items
   int level;
   int at_max;                // 1: no children
+  int shared;                // 1: label and fvals already gathered from the distinct cells
   float dom_lo[3];
   float dom_hi[3];
   const uint64_t* codes;     // [m] cells
@@ -340,6 +341,16 @@ spk_status launch_rays(const spk_net* net, const spk_ray_params& p, int64_t n, c
 spk_status launch_cp_init(int64_t n, uint64_t* codes, uint32_t* qidx, unsigned* best, float* point,
                           hipStream_t stream, int num_cus);
 spk_status launch_cp_round(const spk_net* net, const CpLevel& L, hipStream_t stream, int num_cus);
+// Distinct cells of a round: temporary bytes for m codes; sort + unique into
+// ucodes with the count in *nu (device); then, for the distinct cells U (U.m
+// of them, classified into ulabel), the face values and the gather into every
+// item's label and fvals.
+size_t cp_dedup_temp_bytes(int64_t m);
+spk_status launch_cp_dedup(const uint64_t* codes, uint64_t* sorted, uint64_t* ucodes, int64_t* nu, int64_t m,
+                           int level, void* temp, size_t temp_bytes, hipStream_t stream);
+spk_status launch_cp_shared(const spk_net* net, const CpLevel& U, const uint64_t* codes, int64_t m,
+                            const uint8_t* ulabel, float* ufvals, uint8_t* label, float* fvals, hipStream_t stream,
+                            int num_cus);
 // The batched graph's compaction: zero every item's counts, then compact the
 // labelled cells of every item (one launch each).
 hipError_t launch_batch_compact(const CompactItem* items, const int64_t* prefix, int n_items, int blocks,

@@ -386,6 +386,20 @@ def test_closest_point_edge_cases(ctx):
     assert np.array_equal(b1, bound[:1])
 
 
+def test_closest_point_shared_cells(ctx):
+    """Large rounds classify each distinct cell once and gather the results
+    for every (query, cell) item; a cell's bound and face values do not depend
+    on the query, so 512 queries at once (rounds far above the sharing
+    threshold) give the same bounds, bit for bit, as the same queries two at
+    a time (rounds below it)."""
+    net = wl.tiny_net(0)
+    q = wl.points(512, 44)
+    _, _, b_all = _gpu_closest(ctx, net, q, 7)
+    b_two = np.concatenate([_gpu_closest(ctx, net, q[i:i + 2], 7)[2] for i in range(0, 64, 2)])
+    assert np.array_equal(b_all[:64], b_two)
+    assert np.isfinite(b_all).all()
+
+
 def test_closest_point_chunk_halving(ctx):
     """A workspace limit too small for a 1024-query chunk makes the call
     retry in halves; the bounds equal those of an unlimited context."""
