@@ -204,19 +204,27 @@ def test_general_axes_match_aabb(ctx):
 
 
 def test_eval_points(ctx):
+    """Plain evaluation against the oracle's forward pass; width 256 runs 32
+    points per pass (ragged counts: the pass's tail points are zeros and are
+    not written)."""
     import torch
     from paper_2202_02444_amd import spk
-    for net in (wl.tiny_net(0), wl.scale_net(1), wl.siren_mlp([3, 64, 64, 64, 1], 7, 30.0),
-                wl.he_normal_mlp([3, 128, 128, 1], 8, act="elu")):
+    nets = (wl.tiny_net(0), wl.scale_net(1), wl.siren_mlp([3, 64, 64, 64, 1], 7, 30.0),
+            wl.he_normal_mlp([3, 128, 128, 1], 8, act="elu"), wl.he_normal_mlp([3, 256, 256, 256, 1], 10, act="elu"),
+            wl.siren_mlp([3, 256, 256, 1], 11, 30.0), wl.he_normal_mlp([3, 256, 1], 12))
+    dev = torch.device("cuda")
+    for net in nets:
         g = spk.Net.from_spec(net)
-        x = wl.points(1000, 9)
-        dev = torch.device("cuda")
-        f = torch.empty(1000, device=dev)
-        spk.eval_points(ctx, g, torch.from_numpy(x).to(dev), f)
-        ctx.sync()
-        fo = omlp.forward(net, x)
-        S = max(s_net(net), 1e-30)
-        assert np.max(np.abs(f.cpu().numpy() - fo)) <= TOL * max(S, np.abs(fo).max())
+        for n in (1000, 1, 31, 33):
+            x = wl.points(n, 9 + n)
+            f = torch.full((n + 5,), 7.0, device=dev)
+            spk.eval_points(ctx, g, torch.from_numpy(x).to(dev), f[:n])
+            ctx.sync()
+            fo = omlp.forward(net, x)
+            S = max(s_net(net), 1e-30)
+            out = f.cpu().numpy()
+            assert np.max(np.abs(out[:n] - fo)) <= TOL * max(S, np.abs(fo).max()), (net.name, n)
+            assert np.all(out[n:] == 7.0)   # nothing written past n
 
 
 @pytest.mark.parametrize("act", ["relu", "elu", "sin"])
