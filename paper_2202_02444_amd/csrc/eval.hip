@@ -17,7 +17,9 @@ template <int H, int ACT>
 __global__ __launch_bounds__(64) void eval_kernel(NetDev net, int64_t n, const float* __restrict__ x,
                                                   float* __restrict__ f) {
   constexpr int MT = H / 16;
-  constexpr int NTP = 512 / H;        // 16-point column tiles per pass
+  // 16-point column tiles per pass: activations and accumulators take
+  // 8 MT NTP = 128 registers (twice that spilled)
+  constexpr int NTP = 256 / H;
   constexpr int PPP = 16 * NTP;       // points per pass
   const int lane = threadIdx.x;
   const int g = lane >> 4, c = lane & 15;
@@ -178,7 +180,7 @@ static hipError_t launch_eval_h(const NetDev& net, int64_t n, const float* x, fl
     }
     return hipGetLastError();
   } else {
-    constexpr int PPP = 16 * (512 / H);
+    constexpr int PPP = 16 * (256 / H);
     const int64_t npass = (n + PPP - 1) / PPP;
     int64_t blocks = (int64_t)num_cus * 8;
     if (blocks > npass) blocks = npass;
