@@ -662,6 +662,13 @@ struct CallBuffers {
     for (auto& h : held)
       if (*h.first) (void)hipFreeAsync(*h.first, stream);
   }
+  // Free *p (stream-ordered after the call's earlier launches).
+  void release(void** p, size_t& cap) {
+    if (*p) (void)hipFreeAsync(*p, stream);
+    *p = nullptr;
+    total -= cap;
+    cap = 0;
+  }
   // (Re)allocate *p to at least `bytes`; contents are not kept.
   spk_status ensure(void** p, size_t& cap, size_t bytes) {
     if (bytes <= cap) return SPK_OK;
@@ -820,14 +827,27 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
     }
     job.label = (uint8_t*)labels;
     job.nonfinite = (unsigned long long*)ctx->status;
-    // large rounds: classify and evaluate each distinct cell once
-    const bool shared = m >= kCpShareMin;
+    // large rounds: classify and evaluate each distinct cell once, when the
+    // workspace limit leaves room for the sort (else every item is bounded)
+    bool shared = m >= kCpShareMin;
     int64_t nu = 0;
     if (shared) {
-      SPK_ENSURE(CB.sorted, CB.c_sorted, (size_t)m * 8);
-      SPK_ENSURE(CB.ucodes, CB.c_ucodes, (size_t)m * 8);
       const size_t tb = cp_dedup_temp_bytes(m);
-      SPK_ENSURE(CB.dtemp, CB.c_dtemp, tb);
+      shared = B.ensure(&CB.sorted, CB.c_sorted, (size_t)m * 8) == SPK_OK &&
+               B.ensure(&CB.ucodes, CB.c_ucodes, (size_t)m * 8) == SPK_OK &&
+               B.ensure(&CB.dtemp, CB.c_dtemp, tb) == SPK_OK &&
+               B.ensure(&CB.ulabels, CB.c_ulabels, (size_t)m) == SPK_OK &&
+               B.ensure(&CB.ufvals, CB.c_ufvals, (size_t)m * 6 * 4) == SPK_OK;
+      if (!shared) {
+        // give the room back to the frontier buffers
+        B.release(&CB.sorted, CB.c_sorted);
+        B.release(&CB.ucodes, CB.c_ucodes);
+        B.release(&CB.dtemp, CB.c_dtemp);
+        B.release(&CB.ulabels, CB.c_ulabels);
+        B.release(&CB.ufvals, CB.c_ufvals);
+      }
+    }
+    if (shared) {
       int64_t* dnu = (int64_t*)((char*)cnt + 64);
       st = launch_cp_dedup((const uint64_t*)codes, (uint64_t*)CB.sorted, (uint64_t*)CB.ucodes, dnu, m, level,
                            CB.dtemp, CB.c_dtemp, ctx->stream);
@@ -836,8 +856,6 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
           hipStreamSynchronize(ctx->stream) != hipSuccess)
         return SPK_E_DEVICE;
       if (nu < 1 || nu > m) return SPK_E_DEVICE;
-      SPK_ENSURE(CB.ulabels, CB.c_ulabels, (size_t)nu);
-      SPK_ENSURE(CB.ufvals, CB.c_ufvals, (size_t)nu * 6 * 4);
       job.n = nu;
       job.cells = (const uint64_t*)CB.ucodes;
       job.label = (uint8_t*)CB.ulabels;
