@@ -829,7 +829,7 @@ static spk_status closest_chunk(spk_ctx* ctx, const spk_net* net, const spk_boun
     job.nonfinite = (unsigned long long*)ctx->status;
     // large rounds: classify and evaluate each distinct cell once, when the
     // workspace limit leaves room for the sort (else every item is bounded)
-    bool shared = m >= kCpShareMin;
+    bool shared = m >= kCpShareMin && m <= (int64_t)0x7fffffff;   // the sort counts items in 32 bits
     int64_t nu = 0;
     if (shared) {
       const size_t tb = cp_dedup_temp_bytes(m);
