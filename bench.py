@@ -364,6 +364,14 @@ def full_extra(ctx, g, tlo, thi, dev, n=65536, steps=1):
         res[name] = {"boxes_per_s": n / (ms * 1e-3), "ms": ms, "tflops": tf, "frac_fp32_mfma": tf * 1e12 / PEAK_FP32_MFMA,
                      "classified": float((lab != 0).double().mean().item()),
                      "truncate31_classified": float((labt != 0).double().mean().item())}
+    # the blob's octree to depth 6 with rounding-bounded affine-full cell
+    # bounds against truncate(31) with FP64 products (both sound)
+    for name, pol, prec in (("octree_full_depth6", "full", "f32"), ("octree_truncate_f64_depth6", "truncate", "f64")):
+        t = time.perf_counter()
+        levels, leaves = spk.build_octree(ctx, g, 6, pol, 0 if pol == "full" else K_KEEP, prec=prec)
+        torch.cuda.synchronize()
+        res[name] = {"seconds": time.perf_counter() - t, "frontier": [lv["n"] for lv in levels],
+                     "leaves": int(leaves.shape[0])}
     return res
 
 
@@ -634,9 +642,10 @@ def main():
             progress("batched done")
         if "precision" in which:
             extra["precision"] = precision_extra(ctx, g, net, tlo, thi, lo, hi, dev)
+            progress("precision done")
         if "full" in which:
             extra["affine_full"] = full_extra(ctx, g, tlo, thi, dev)
-            progress("precision done")
+            progress("affine-full done")
         if "serving" in which:
             extra["serving"] = serving_extra(dev)
             progress("serving done")
