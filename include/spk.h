@@ -62,12 +62,13 @@ typedef enum { SPK_ACT_RELU = 0, SPK_ACT_ELU = 1, SPK_ACT_SIN = 2 } spk_act;
  *  SPK_AFFINE_FIXED     every new term goes into the condensed term.
  *  SPK_AFFINE_TRUNCATE  the k largest terms are kept (3 <= k <= 31).
  *  SPK_AFFINE_FULL      every term is kept: the generator matrix grows by the
- *                       hidden width at each activation.  Hidden width 256 and
- *                       SPK_PREC_F32 only (else SPK_E_UNSUPPORTED); each call
- *                       allocates, stream-ordered on the context's stream, a
- *                       workspace of min(n, 4 x CUs) x 256 x (32 + 256 (L-2))
- *                       floats (L linear layers; 1.9 GB for 8 hidden layers on
- *                       256 CUs), SPK_E_NOMEM if that fails.  The rounding-
+ *                       hidden width at each activation.  Hidden width 128 or
+ *                       256 and SPK_PREC_F32 only (else SPK_E_UNSUPPORTED);
+ *                       each call allocates, stream-ordered on the context's
+ *                       stream, a workspace of min(n, 4 x CUs) x H x
+ *                       (32 + H (L-2)) floats (L linear layers; 1.9 GB for
+ *                       H = 256 and 8 hidden layers on 256 CUs), SPK_E_NOMEM
+ *                       if that fails.  The rounding-
  *                       bounded mode puts every rounding into the new term of
  *                       its neuron.  Not available to spk_batch_create or
  *                       spk_subdivide_frontier_noalloc (SPK_E_UNSUPPORTED). */

@@ -1,6 +1,7 @@
 // Range bound with the affine-full policy (Section 3.3: no condensation; every
 // nonlinearity adds one new term per neuron and all of them are kept) on
-// gfx950, for hidden width 256, one box per wavefront.
+// gfx950, for hidden width 128 or 256, one box per wavefront (at width 128
+// lanes 32..63 own no rows and only join the matrix-core sweep).
 //
 // The generator matrix of a box grows by H columns per hidden layer (3 input
 // axes, then one diagonal block per activation), to 32 + (L - 2) H columns,
@@ -48,12 +49,24 @@ namespace spk {
 
 namespace {
 
-using FS = Shape<256, 2>;   // 32-column tiles, one box per wave
-constexpr int kH = 256;
+// One box per wave at hidden width HW: HW/16 row tiles, two 16-column tiles
+// of generators, rows 4ch..4ch+3 owned by lane ch < HW/4.
+template <int HW>
+struct FShape {
+  static constexpr int H = HW;
+  static constexpr int MT = HW / 16;
+  static constexpr int NT = 2;
+  static constexpr int NS = 32;
+  static constexpr int BPW = 1;
+  static constexpr int SEG = HW / 4;
+  static constexpr int TILE = NS * HW;
+  static constexpr int SWM = ((HW / 4) < 16 ? (HW / 4) : 16) - 1;
+};
 
+template <int HW>
 struct FullLds {
-  LdsState<FS> st;     // B tile of 32 columns, and the vectors x' (vc), v (vinf)
-  float gam[kH];       // new-term radii gamma' of the last activation
+  LdsState<FShape<HW>> st;   // B tile of 32 columns, and the vectors x' (vc), v (vinf)
+  float gam[HW];             // new-term radii gamma' of the last activation
 };
 
 // Table 3 activation of the four rows of this lane.  In: x (FP64 pre-activation
@@ -106,11 +119,13 @@ __device__ __forceinline__ void act_full(double (&x)[4], const double (&rY)[4], 
   }
 }
 
-template <int ACT>
+template <int kH, int ACT>
 __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, float* ws, int64_t ncap) {
-  __shared__ __attribute__((aligned(16))) FullLds sm;
+  using FS = FShape<kH>;
+  __shared__ __attribute__((aligned(16))) FullLds<kH> sm;
   const int lane = (int)threadIdx.x;
   const int ch = lane;
+  const bool own = ch < kH / 4;   // lane owns rows 4ch..4ch+3
   const int L = net.L;
   const bool rig = job.rigorous != 0;
   float* Yw = ws + (size_t)blockIdx.x * (size_t)kH * (size_t)ncap;   // this wave's generator matrix
@@ -133,7 +148,9 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
     // ---- layer 0 (3 -> H): center, axis generators, input error ----
     double x[4], rY[4], e[4];
     float al[4], g[4], v[4];
-    {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = rY[i] = e[i] = 0.0;
+    if (own) {
       double xc[4];
       f4 y[16];
       float yinf[4], e0[4];
@@ -153,17 +170,27 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
       }
     }
     act_full<ACT>(x, rY, e, net.omega0, rig, net.cK, net.cD, al, g, v);
+    if (!own) {
+      // lanes without rows carry zeros
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        x[i] = rY[i] = 0.0;
+        al[i] = g[i] = v[i] = 0.0f;
+      }
+    }
     int64_t ncols = 32;
     // ---- hidden layers ----
 #pragma unroll 1
     for (int a = 0; a < L - 2; ++a) {
       // the previous activation's center, rounding vector and new-term radii
       // for every lane
+      if (own) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        sm.st.vc[4 * ch + i] = x[i];
-        sm.st.vinf[4 * ch + i] = v[i];
-        sm.gam[4 * ch + i] = g[i];
+        for (int i = 0; i < 4; ++i) {
+          sm.st.vc[4 * ch + i] = x[i];
+          sm.st.vinf[4 * ch + i] = v[i];
+          sm.gam[4 * ch + i] = g[i];
+        }
       }
       __syncthreads();
       // row-owner sweep over W (4x4 blocks): FP64 center, |W| v, and the new
@@ -179,7 +206,7 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
         pe[i] = 0.0f;
       }
 #pragma unroll 1
-      for (int kb = 0; kb < kH / 4; kb += 2) {
+      for (int kb = 0; kb < (own ? kH / 4 : 0); kb += 2) {
         f4 w[2][4];
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -215,7 +242,7 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
         __syncthreads();
         // eight columns' loads in flight per step
 #pragma unroll 1
-        for (int C0 = 0; C0 < 32; C0 += 8) {
+        for (int C0 = 0; C0 < (own ? 32 : 0); C0 += 8) {
           f4 buf[8];
 #pragma unroll
           for (int q = 0; q < 8; ++q) buf[q] = __builtin_nontemporal_load((const f4*)&T[(size_t)(C0 + q) * kH]);
@@ -229,18 +256,21 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
         }
         __syncthreads();
         single_box_pass2<FS, VA_NONE>(sm.st, Wl, lane);
+        if (own) {
 #pragma unroll
-        for (int C = 0; C < 32; ++C) {
-          const f4 val = *(const f4*)&sm.st.tile[taddr<FS>(0, C, ch)];
+          for (int C = 0; C < 32; ++C) {
+            const f4 val = *(const f4*)&sm.st.tile[taddr<FS>(0, C, ch)];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) rs[i] += (double)fabsf(val[i]);
-          *(f4*)&T[(size_t)C * kH] = val;
+            for (int i = 0; i < 4; ++i) rs[i] += (double)fabsf(val[i]);
+            *(f4*)&T[(size_t)C * kH] = val;
+          }
         }
       }
       ncols += kH;
       // pre-activation rows of the next activation
-      const f4 bh = *(const f4*)&net.bh[(size_t)a * kH + 4 * ch];
-      const f4 eb = *(const f4*)&net.ebh[(size_t)a * kH + 4 * ch];
+      const f4 f0 = {0.0f, 0.0f, 0.0f, 0.0f};
+      const f4 bh = own ? *(const f4*)&net.bh[(size_t)a * kH + 4 * ch] : f0;
+      const f4 eb = own ? *(const f4*)&net.ebh[(size_t)a * kH + 4 * ch] : f0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         x[i] = c0[i] + (double)bh[i];
@@ -255,10 +285,17 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
         }
       }
       act_full<ACT>(x, rY, e, net.omega0, rig, net.cK, net.cD, al, g, v);
+      if (!own) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x[i] = rY[i] = 0.0;
+          al[i] = g[i] = v[i] = 0.0f;
+        }
+      }
     }
     // ---- output layer: center, sum over the stored columns of |w . alpha Y|,
     // and the last activation's new terms ----
-    const f4 wv = *(const f4*)&net.wL[4 * ch];
+    const f4 wv = own ? *(const f4*)&net.wL[4 * ch] : (f4){0.0f, 0.0f, 0.0f, 0.0f};
     float wa[4];
     double y0 = 0.0, rg = 0.0, perr = 0.0, cabs = 0.0;
 #pragma unroll
@@ -278,8 +315,10 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
     for (int64_t c0t = 0; c0t < ncols; c0t += 32) {
       const float* T = Yw + (size_t)c0t * kH + 4 * ch;
       float p[32];
+#pragma unroll
+      for (int C = 0; C < 32; ++C) p[C] = 0.0f;
 #pragma unroll 1
-      for (int C0 = 0; C0 < 32; C0 += 8) {
+      for (int C0 = 0; C0 < (own ? 32 : 0); C0 += 8) {
         f4 buf[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) buf[q] = __builtin_nontemporal_load((const f4*)&T[(size_t)(C0 + q) * kH]);
@@ -328,27 +367,42 @@ __global__ __launch_bounds__(64, 1) void full_kernel(NetDev net, BoundJob job, f
 }  // namespace
 
 // Columns of one box's generator matrix under affine-full.
-int64_t full_columns(int L) { return 32 + (int64_t)(L - 2) * kH; }
+static int64_t full_columns(int L, int H) { return 32 + (int64_t)(L - 2) * H; }
+
+template <int HW>
+static void launch_full_h(const NetDev& d, const BoundJob& job, float* ws, int64_t ncap, int64_t blocks,
+                          hipStream_t stream) {
+  switch (d.act) {
+    case SPK_ACT_RELU:
+      hipLaunchKernelGGL((full_kernel<HW, SPK_ACT_RELU>), dim3((unsigned)blocks), dim3(64), 0, stream, d, job, ws, ncap);
+      break;
+    case SPK_ACT_ELU:
+      hipLaunchKernelGGL((full_kernel<HW, SPK_ACT_ELU>), dim3((unsigned)blocks), dim3(64), 0, stream, d, job, ws, ncap);
+      break;
+    default:
+      hipLaunchKernelGGL((full_kernel<HW, SPK_ACT_SIN>), dim3((unsigned)blocks), dim3(64), 0, stream, d, job, ws, ncap);
+      break;
+  }
+}
 
 spk_status launch_full(const spk_net* net, const BoundJob& job, hipStream_t stream, int num_cus) {
   const NetDev& d = net->dev;
-  if (d.H != kH || job.prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;
+  if ((d.H != 256 && d.H != 128) || job.prec != SPK_PREC_F32) return SPK_E_UNSUPPORTED;
   if (job.n <= 0) return SPK_OK;
   int64_t blocks = (int64_t)num_cus * 4;
   if (blocks > job.n) blocks = job.n;
   if (blocks < 1) blocks = 1;
-  const int64_t ncap = full_columns(d.L);
-  const size_t bytes = (size_t)blocks * (size_t)kH * (size_t)ncap * sizeof(float);
+  const int64_t ncap = full_columns(d.L, d.H);
+  const size_t bytes = (size_t)blocks * (size_t)d.H * (size_t)ncap * sizeof(float);
   float* ws = nullptr;
   if (hipMallocAsync((void**)&ws, bytes, stream) != hipSuccess) {
     (void)hipGetLastError();
     return SPK_E_NOMEM;
   }
-  switch (d.act) {
-    case SPK_ACT_RELU: hipLaunchKernelGGL(full_kernel<SPK_ACT_RELU>, dim3((unsigned)blocks), dim3(64), 0, stream, d, job, ws, ncap); break;
-    case SPK_ACT_ELU: hipLaunchKernelGGL(full_kernel<SPK_ACT_ELU>, dim3((unsigned)blocks), dim3(64), 0, stream, d, job, ws, ncap); break;
-    default: hipLaunchKernelGGL(full_kernel<SPK_ACT_SIN>, dim3((unsigned)blocks), dim3(64), 0, stream, d, job, ws, ncap); break;
-  }
+  if (d.H == 256)
+    launch_full_h<256>(d, job, ws, ncap, blocks, stream);
+  else
+    launch_full_h<128>(d, job, ws, ncap, blocks, stream);
   const hipError_t err = hipGetLastError();
   (void)hipFreeAsync(ws, stream);   // ordered after the launch on the stream
   return err == hipSuccess ? SPK_OK : SPK_E_DEVICE;

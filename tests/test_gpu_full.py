@@ -3,8 +3,8 @@ new term kept) against the FP64 oracle's full policy, through the C ABI.
 Tolerances as for the other policies: raw endpoints within 1e-5 * S in the
 paper's arithmetic, labels equal outside the ambiguity band, the rounding-
 bounded bound containing the oracle's exact bound, and every sampled f inside
-the returned bound.  Hidden width 256 (one box per wave); other widths and
-the split precisions return SPK_E_UNSUPPORTED."""
+the returned bound.  Hidden widths 128 and 256 (one box per wave); other
+widths and the split precisions return SPK_E_UNSUPPORTED."""
 import numpy as np
 import pytest
 
@@ -27,8 +27,8 @@ def ctx():
     c.close()
 
 
-def _net(act, depth, seed):
-    widths = [3] + [256] * depth + [1]
+def _net(act, depth, seed, width=256):
+    widths = [3] + [width] * depth + [1]
     if act == "sin":
         return wl.siren_mlp(widths, seed, omega0=30.0)
     return wl.he_normal_mlp(widths, seed, act=act)
@@ -62,12 +62,13 @@ def _check(ctx, net, lo, hi, rng, name, sample=None):
     return out, outr, (lo_o, hi_o)
 
 
+@pytest.mark.parametrize("width", [128, 256])
 @pytest.mark.parametrize("act", ["relu", "elu", "sin"])
 @pytest.mark.parametrize("depth", [1, 2, 3])
-def test_full_parity(ctx, act, depth):
-    net = _net(act, depth, 40 + depth)
+def test_full_parity(ctx, act, depth, width):
+    net = _net(act, depth, 40 + depth, width)
     lo, hi = wl.boxes(96, 70 + depth, 1e-3, 0.3)
-    _check(ctx, net, lo, hi, np.random.default_rng(5), "%s 256x%d" % (act, depth))
+    _check(ctx, net, lo, hi, np.random.default_rng(5), "%s %dx%d" % (act, width, depth))
 
 
 def test_full_blob_8x256(ctx):
@@ -120,10 +121,11 @@ def test_full_unsupported_widths_and_precisions(ctx):
     tl = torch.from_numpy(lo).to(dev)
     th = torch.from_numpy(hi).to(dev)
     lab = torch.empty(4, dtype=torch.uint8, device=dev)
-    g = spk.Net.from_spec(wl.tiny_net(0))   # width 32
-    with pytest.raises(spk.SpkError) as e:
-        spk.classify_boxes(ctx, g, tl, th, lab, policy="full", k=0)
-    assert e.value.status == spk.E_UNSUPPORTED
+    for net in (wl.tiny_net(0), wl.he_normal_mlp([3, 64, 64, 1], 3)):   # widths 32 and 64
+        g = spk.Net.from_spec(net)
+        with pytest.raises(spk.SpkError) as e:
+            spk.classify_boxes(ctx, g, tl, th, lab, policy="full", k=0)
+        assert e.value.status == spk.E_UNSUPPORTED
     g = spk.Net.from_spec(_net("relu", 1, 0))
     with pytest.raises(spk.SpkError) as e:
         spk.classify_boxes(ctx, g, tl, th, lab, policy="full", k=0, prec="bf16x3")
