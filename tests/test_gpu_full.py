@@ -179,3 +179,38 @@ def test_full_rejected_by_noalloc(ctx):
     with pytest.raises(spk.SpkError) as e:
         spk.subdivide_frontier(ctx, g, 0, cells, children, None, counts, 3, "full", 0, noalloc=True)
     assert e.value.status == spk.E_UNSUPPORTED
+
+
+def test_full_closest_point_octahedron(ctx):
+    """Closest point (Section 4.10) with affine-full cell bounds, rounding-
+    bounded, on the exact octahedron |x|_1 - R padded to width 128: every
+    returned bound is at least the true distance and the candidate lies within
+    one cell diagonal of it."""
+    import math
+    import torch
+    from paper_2202_02444_amd import spk
+    R, L = 0.55, 5
+    net = wl.octahedron_mlp(R, pad_to=128)
+    g = spk.Net.from_spec(net)
+    dev = torch.device("cuda")
+    q = wl.points(64, 45)
+    n = q.shape[0]
+    pt = torch.empty((n, 3), device=dev)
+    dist = torch.empty(n, device=dev)
+    bound = torch.empty(n, device=dev)
+    spk.closest_point(ctx, g, torch.from_numpy(q).to(dev), pt, dist, bound, max_level=L, policy="full", k=0)
+    ctx.sync()
+    b, d = bound.cpu().numpy().astype(np.float64), dist.cpu().numpy().astype(np.float64)
+    diag = math.sqrt(3.0) * 2.0 / (1 << L)
+    for i in range(n):
+        ax = np.sort(np.abs(q[i].astype(np.float64)))[::-1]
+        s = ax.sum()
+        if s <= R:
+            dstar = (R - s) / math.sqrt(3.0)
+        else:
+            cs = np.cumsum(ax)
+            rho = max(j for j in range(3) if ax[j] - (cs[j] - R) / (j + 1) > 0)
+            tau = (cs[rho] - R) / (rho + 1)
+            dstar = float(np.linalg.norm(np.abs(q[i]) - np.maximum(np.abs(q[i]) - tau, 0.0)))
+        assert b[i] >= dstar - 1e-5, (i, b[i], dstar)
+        assert d[i] <= dstar + diag + 1e-5, (i, d[i], dstar)
