@@ -70,8 +70,9 @@ typedef enum { SPK_ACT_RELU = 0, SPK_ACT_ELU = 1, SPK_ACT_SIN = 2 } spk_act;
  *                       H = 256 and 8 hidden layers on 256 CUs), SPK_E_NOMEM
  *                       if that fails.  The rounding-
  *                       bounded mode puts every rounding into the new term of
- *                       its neuron.  Not available to spk_batch_create or
- *                       spk_subdivide_frontier_noalloc (SPK_E_UNSUPPORTED). */
+ *                       its neuron.  Not available to spk_batch_create,
+ *                       spk_subdivide_frontier_noalloc or the server
+ *                       (SPK_E_UNSUPPORTED). */
 typedef enum { SPK_AFFINE_FIXED = 0, SPK_AFFINE_TRUNCATE = 1, SPK_AFFINE_FULL = 2 } spk_policy;
 
 /* Arithmetic of the generator products Y = W X of the hidden layers.
@@ -568,7 +569,9 @@ spk_status spk_batch_destroy(spk_batch* batch);
  *                     point shrinks its query chunks to fit; SPK_E_NOMEM when
  *                     one query's frontier does not fit).  Beyond that the
  *                     workers hold only their contexts' few hundred bytes of
- *                     scratch and status.
+ *                     scratch and status.  Requests with SPK_AFFINE_FULL are
+ *                     refused (SPK_E_UNSUPPORTED at submit): that policy
+ *                     allocates its workspace outside the budget.
  * spk_server_poll returns up to max completions (wait != 0: block until one is
  * available or nothing is queued or running).  spk_server_destroy waits for
  * every queued and running request, then stops the workers.

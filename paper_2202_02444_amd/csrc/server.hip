@@ -179,6 +179,10 @@ spk_status spk_server_submit(spk_server* s, const spk_request* req, uint64_t* id
   if (req->n > 0 && (req->a == nullptr || req->out0 == nullptr)) return SPK_E_INVAL;
   if ((req->type == SPK_REQ_CLASSIFY || req->type == SPK_REQ_RAYS) && req->n > 0 && req->b == nullptr)
     return SPK_E_INVAL;
+  // affine-full allocates its own workspace per call, outside the admission
+  // budget: not served
+  if ((req->type == SPK_REQ_CLASSIFY || req->type == SPK_REQ_CLOSEST) && req->opts.policy == SPK_AFFINE_FULL)
+    return SPK_E_UNSUPPORTED;
   Pending p;
   p.req = *req;
   p.submit_s = now_s();

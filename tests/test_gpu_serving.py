@@ -142,3 +142,22 @@ def test_request_workspace_stays_within_declared_bytes(env):
         assert 0 < c["workspace_bytes"] <= ws, (c["workspace_bytes"], ws)
         for k in OUT_KEYS["closest"]:
             np.testing.assert_array_equal(r[k].cpu().numpy(), a[k])
+
+
+def test_affine_full_requests_refused(env):
+    """Affine-full allocates its workspace per call, outside the admission
+    budget, so the server refuses such requests at submit."""
+    import torch
+    spk, nets, ctx = env
+    dev = torch.device("cuda")
+    lo = torch.zeros((4, 3), device=dev)
+    hi = torch.ones((4, 3), device=dev)
+    lab = torch.empty(4, dtype=torch.uint8, device=dev)
+    srv = spk.Server(nets, 1 << 30, 1)
+    try:
+        with pytest.raises(spk.SpkError) as e:
+            srv.submit({"type": "classify", "net": 0, "box_lo": lo, "box_hi": hi, "label": lab, "policy": "full",
+                        "k": 0})
+        assert e.value.status == spk.E_UNSUPPORTED
+    finally:
+        srv.close()
